@@ -1,0 +1,820 @@
+"""Plain FP64 CPU oracle of PDNQP (proximal ALM outer loop + practical
+diagonal adaptive restarted accelerated PDHG inner solver).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and
+the benchmark's CPU-baseline leg may import or run this file.  The product
+path (the HIP library and its Python binding) never calls it, and this file
+imports nothing from the product package.
+
+Written from the paper's text: Section 2 (problem (qp), proximal ALM,
+residual form, inner QP (inner-qp)/(inner-bounds)), Section 3.1
+(initialisation, gamma choice (R-choice), outer Ruiz scaling
+(scaled-problem)), Section 3.2 (Algorithm "practical outer iteration",
+multiplier update (practical-multiplier-update), residuals
+(outer-residuals)/(outer-scales)/(outer-termination), penalty trigger
+(penalty-trigger-eq), inner-tolerance factor (inner-tolerance-factor),
+centre update (center-update)/(center-tolerance-update)), Section 3.3
+(Algorithm "practical diagonal PDHG", warm start (inner-warm-start),
+penalty scaling (inner-penalty-scaling), inner Ruiz scaling, inner
+termination (inner-residuals)/(inner-scales)/(inner-termination), primal
+weight (primal-weight-movement)/(primal-weight-update), diagonal steps
+(diagonal-scales)/(diagonal-steps), trial step (pdqp-trial), acceptance
+(adaptive-condition), restart), and the default parameter table.
+
+Everything here is evaluated literally in the coordinates the paper uses:
+the inner QP is formed explicitly as sparse block matrices, penalty-scaled,
+Ruiz-scaled, and iterated in those scaled ("hatted") coordinates.  Sparse
+matrix-vector products (scipy) and a tridiagonal eigenvalue routine are the
+only library primitives used.
+
+Where the paper leaves a choice open, the reading taken is a field of
+``Settings`` and is marked ``[reading]`` in the docstring that uses it.
+Parity status of each reading: the restart rule, N_p = N_d, the rejection
+shrink factor, the initial primal weight, the objective scalar, the initial
+penalty, and the penalty growth factor are "parity unpinned" (the paper
+fixes no value to check against); the tests pin the mathematics around them
+(fixed point = KKT, brute-force minimisers, closed forms, invariants).
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.linalg import eigvalsh_tridiagonal
+
+# Status codes (shared meaning with the library's public header).
+SOLVED = 1
+MAX_ITER = 2
+TIME_LIMIT = 3
+NUMERICAL_ERROR = 4
+
+INNER_CONVERGED = 0
+INNER_ITER_LIMIT = 1
+INNER_NUMERICAL_ERROR = 2
+INNER_TIME_LIMIT = 3
+
+
+@dataclass
+class Settings:
+    # Default parameter table of the paper.
+    eps_abs: float = 1e-4
+    eps_rel: float = 1e-4
+    max_outer: int = 2**31 - 1
+    max_inner: int = 40000
+    time_limit: float = math.inf
+    sigma_init: float = 20.0
+    theta_sigma: float = 0.25
+    delta_gamma: float = 1e-2
+    rho_in_min: float = 0.3
+    rho_in_max: float = 0.95
+    rho_z: float = 0.95
+    ruiz_sweeps: int = 8
+    # [reading] restart cadence and thresholds (PDLP-style KKT restarts)
+    check_every: int = 64
+    restart_suff: float = 0.2
+    restart_nec: float = 0.8
+    restart_art: float = 0.36
+    # [reading] rejection shrink factor clamp(safety * L / R, lo, hi), limit
+    shrink_safety: float = 0.95
+    shrink_min: float = 0.1
+    shrink_max: float = 0.9
+    max_rejects: int = 50
+    # [reading] initial primal weight
+    omega0: float = 1.0
+    # [reading] penalty growth and clamps
+    sigma_growth: float = 10.0
+    sigma_max: float = 1e9
+    sigma0_min: float = 1e-4
+    sigma0_max: float = 1e4
+    # [reading] a row whose residual already meets the outer tolerance
+    # (|r_i| <= eps_abs + eps_rel * s_p) is not penalised further
+    penalty_gate: bool = True
+    # [reading] Lanczos steps for the smallest eigenvalue of Q
+    lanczos_iters: int = 100
+    gamma_override: float = 0.0
+    # test knob: multiplies the diagonal steps at every rebuild (1 = paper)
+    step_boost: float = 1.0
+    outer_scaling: int = 0
+
+
+# ---------------------------------------------------------------------------
+# Problem normalisation: rows rl <= a'x <= ru into the paper's form (qp)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Normalised:
+    n: int
+    m_e: int
+    m_i: int
+    Q: sp.csr_matrix
+    c: np.ndarray
+    A: sp.csr_matrix          # internal rows: equalities first, then >= rows
+    b: np.ndarray
+    xl: np.ndarray
+    xu: np.ndarray
+    row_of: np.ndarray        # original row of each internal row
+    sign_of: np.ndarray       # +1 / -1 (row negated for an upper bound)
+
+
+def normalise(prob):
+    """Classify rows into A_E x = b_E and A_I x >= b_I (problem (qp)).
+
+    rl == ru -> equality; only rl finite -> ``>=`` row; only ru finite ->
+    negated ``>=`` row; both finite with rl < ru -> two ``>=`` rows; both
+    infinite -> dropped.  Equality rows come first, each group in original
+    order.
+    """
+    A = sp.csr_matrix(prob["A"])
+    rl = np.asarray(prob["rl"], float)
+    ru = np.asarray(prob["ru"], float)
+    m = A.shape[0]
+    e_rows, i_rows, i_sign, i_b = [], [], [], []
+    for j in range(m):
+        lo, hi = rl[j], ru[j]
+        if lo == hi:
+            continue
+        if np.isfinite(lo):
+            i_rows.append(j); i_sign.append(1.0); i_b.append(lo)
+        if np.isfinite(hi):
+            i_rows.append(j); i_sign.append(-1.0); i_b.append(-hi)
+    e_rows = [j for j in range(m) if rl[j] == ru[j]]
+    rows = np.array(e_rows + i_rows, dtype=np.int64)
+    signs = np.array([1.0] * len(e_rows) + i_sign)
+    b = np.concatenate([rl[e_rows], np.array(i_b, float)])
+    Aint = sp.csr_matrix(sp.diags(signs) @ A[rows]) if rows.size else \
+        sp.csr_matrix((0, A.shape[1]))
+    return Normalised(n=A.shape[1], m_e=len(e_rows), m_i=len(i_rows),
+                      Q=sp.csr_matrix(prob["Q"]), c=np.asarray(prob["c"], float),
+                      A=Aint, b=b, xl=np.asarray(prob["xl"], float),
+                      xu=np.asarray(prob["xu"], float), row_of=rows, sign_of=signs)
+
+
+# ---------------------------------------------------------------------------
+# Ruiz equilibration (Section 3.1, eq. (scaled-problem); also used on the
+# inner constraint matrix in Section 3.3)
+# ---------------------------------------------------------------------------
+
+def ruiz(M, sweeps):
+    """Row/column infinity-norm equilibration of a sparse matrix.
+
+    Each sweep divides every row of the current scaled matrix by the square
+    root of its infinity norm and every column by the square root of its
+    infinity norm, both measured on the matrix before the sweep.  A zero
+    row or column keeps its scale.  Returns (row_scale, col_scale) with
+    scaled matrix diag(row_scale) M diag(col_scale).
+    """
+    M = sp.csr_matrix(abs(sp.csr_matrix(M)))
+    mr, nc = M.shape
+    dr = np.ones(mr)
+    dc = np.ones(nc)
+    for _ in range(sweeps):
+        S = sp.diags(dr) @ M @ sp.diags(dc)
+        S = sp.csr_matrix(S)
+        rn = S.max(axis=1).toarray().ravel() if mr else np.zeros(0)
+        cn = S.max(axis=0).toarray().ravel() if mr else np.zeros(nc)
+        dr = dr / np.sqrt(np.where(rn > 0, rn, 1.0))
+        dc = dc / np.sqrt(np.where(cn > 0, cn, 1.0))
+    return dr, dc
+
+
+@dataclass
+class Scaled:
+    """Outer-scaled problem: bar A = Dc A Dx, objective times c_obj."""
+    n: int
+    m_e: int
+    m_i: int
+    Q: sp.csr_matrix
+    c: np.ndarray
+    A: sp.csr_matrix
+    b: np.ndarray
+    xl: np.ndarray
+    xu: np.ndarray
+    Dc: np.ndarray
+    Dx: np.ndarray
+    c_obj: float
+
+
+SCALE_RUIZ_A = 0
+SCALE_NONE = 1
+SCALE_RUIZ_QA = 2
+
+
+def ruiz_with_q(A, Q, sweeps):
+    """Ruiz sweeps in which a column's infinity norm is the larger of its
+    norm in the scaled A and in the symmetrically scaled Q (Dx Q Dx); row
+    scales come from A alone."""
+    Aa = sp.csr_matrix(abs(sp.csr_matrix(A)))
+    Qa = sp.csr_matrix(abs(sp.csr_matrix(Q)))
+    mr, nc = Aa.shape
+    dr = np.ones(mr)
+    dc = np.ones(nc)
+    for _ in range(sweeps):
+        SA = sp.csr_matrix(sp.diags(dr) @ Aa @ sp.diags(dc))
+        SQ = sp.csr_matrix(sp.diags(dc) @ Qa @ sp.diags(dc))
+        rn = SA.max(axis=1).toarray().ravel() if mr else np.zeros(0)
+        cn = SA.max(axis=0).toarray().ravel() if mr else np.zeros(nc)
+        cn = np.maximum(cn, SQ.max(axis=0).toarray().ravel())
+        dr = dr / np.sqrt(np.where(rn > 0, rn, 1.0))
+        dc = dc / np.sqrt(np.where(cn > 0, cn, 1.0))
+    return dr, dc
+
+
+def outer_scale(P: Normalised, x0, sweeps, mode=SCALE_RUIZ_A):
+    """Section 3.1: Ruiz on the combined constraint matrix, the same
+    transformation applied to objective, right-hand sides and bounds, plus
+    one objective scalar.
+
+    [reading] objective scalar c_obj = 1 / max(1, ||Dx (Q x0 + c)||_inf)
+    (gradient size at the start point in scaled variables).
+    ``mode`` selects the paper's scaling (SCALE_RUIZ_A), none, or the
+    variant whose column norms also count Q (SCALE_RUIZ_QA).
+    """
+    if mode == SCALE_RUIZ_A:
+        Dc, Dx = ruiz(P.A, sweeps)
+    elif mode == SCALE_RUIZ_QA:
+        Dc, Dx = ruiz_with_q(P.A, P.Q, sweeps)
+    else:
+        Dc, Dx = np.ones(P.m_e + P.m_i), np.ones(P.n)
+    g0 = Dx * (P.Q @ x0 + P.c)
+    c_obj = 1.0 / max(1.0, float(np.max(np.abs(g0))) if P.n else 1.0)
+    DxM = sp.diags(Dx)
+    Qs = sp.csr_matrix(c_obj * (DxM @ P.Q @ DxM))
+    As = sp.csr_matrix(sp.diags(Dc) @ P.A @ DxM)
+    return Scaled(n=P.n, m_e=P.m_e, m_i=P.m_i, Q=Qs, c=c_obj * Dx * P.c,
+                  A=As, b=Dc * P.b, xl=P.xl / Dx, xu=P.xu / Dx,
+                  Dc=Dc, Dx=Dx, c_obj=c_obj)
+
+
+# ---------------------------------------------------------------------------
+# Proximal step gamma (Section 3.1, eq. (R-choice))
+# ---------------------------------------------------------------------------
+
+def lanczos_min_eig(Q, iters):
+    """Smallest Ritz value of plain Lanczos (three-term recurrence, no
+    reorthogonalisation) started from the normalised all-ones vector.
+
+    [reading] start vector 1/sqrt(n); the recurrence stops early when the
+    new off-diagonal falls to 1e-14 * max(1, ||Q||_inf) (invariant subspace).
+    """
+    n = Q.shape[0]
+    k = min(iters, n)
+    qnorm = max(1.0, float(abs(Q).sum(axis=1).max())) if n else 1.0
+    v = np.full(n, 1.0 / math.sqrt(n))
+    v_prev = np.zeros(n)
+    beta_prev = 0.0
+    alphas, betas = [], []
+    for j in range(k):
+        w = Q @ v
+        alpha = float(v @ w)
+        w = w - alpha * v - beta_prev * v_prev
+        beta = float(np.linalg.norm(w))
+        alphas.append(alpha)
+        if j == k - 1 or beta <= 1e-14 * qnorm:
+            break
+        betas.append(beta)
+        v_prev, v, beta_prev = v, w / beta, beta
+    if len(alphas) == 1:
+        return alphas[0]
+    return float(eigvalsh_tridiagonal(np.array(alphas), np.array(betas),
+                                      select="i", select_range=(0, 0))[0])
+
+
+def choose_gamma(Qs, st: Settings):
+    """gamma = 1 / (-lambda_hat + delta_gamma * max(1, ||Q||_inf)).
+
+    [reading] ||Q||_inf is the maximum absolute row sum; -lambda_hat is
+    clamped at 0 so that a convex Q gives gamma = 1/(delta_gamma max(1,..)).
+    """
+    if st.gamma_override > 0:
+        return st.gamma_override, float("nan")
+    lam = lanczos_min_eig(Qs, st.lanczos_iters)
+    qn = float(abs(Qs).sum(axis=1).max()) if Qs.shape[0] else 0.0
+    return 1.0 / (max(0.0, -lam) + st.delta_gamma * max(1.0, qn)), lam
+
+
+def initial_penalty(S: Scaled, x0s, st: Settings):
+    """[reading] Uniform initial row penalty in the manner of QPALM:
+    sigma0 = clip(sigma_init * max(1, |f(x0)|) / max(1, 0.5 ||A x0 - P_C(A x0)||^2),
+    sigma0_min, sigma0_max), with P_C the projection onto the feasible row
+    values (b on equality rows, [b, inf) on inequality rows).
+    """
+    f = 0.5 * float(x0s @ (S.Q @ x0s)) + float(S.c @ x0s)
+    ax = S.A @ x0s
+    proj = np.concatenate([S.b[:S.m_e], np.maximum(S.b[S.m_e:], ax[S.m_e:])])
+    viol = ax - proj
+    val = st.sigma_init * max(1.0, abs(f)) / max(1.0, 0.5 * float(viol @ viol))
+    val = min(max(val, st.sigma0_min), st.sigma0_max)
+    return np.full(S.m_e + S.m_i, val)
+
+
+# ---------------------------------------------------------------------------
+# Inner QP (Section 2.2, eq. (inner-qp), (inner-bounds))
+# ---------------------------------------------------------------------------
+
+@dataclass
+class InnerQP:
+    """min 1/2 w'Hw + q'w s.t. Bw = h, lo <= w <= hi, w = (x, s_I, r_E, r_I)."""
+    n: int
+    m_e: int
+    m_i: int
+    H: sp.csr_matrix
+    q: np.ndarray
+    B: sp.csr_matrix
+    h: np.ndarray
+    lo: np.ndarray
+    hi: np.ndarray
+
+
+def form_inner_qp(S: Scaled, z, lam, sigma, gamma):
+    n, me, mi = S.n, S.m_e, S.m_i
+    m = me + mi
+    AE = S.A[:me]
+    AI = S.A[me:]
+    B = sp.bmat([[AE, sp.csr_matrix((me, mi)), -sp.identity(me), sp.csr_matrix((me, mi))],
+                 [AI, -sp.identity(mi), sp.csr_matrix((mi, me)), -sp.identity(mi)]],
+                format="csr") if m else sp.csr_matrix((0, n))
+    H = sp.block_diag([S.Q + sp.identity(n) / gamma, sp.csr_matrix((mi, mi)),
+                       sp.diags(sigma[:me]) if me else sp.csr_matrix((0, 0)),
+                       sp.diags(sigma[me:]) if mi else sp.csr_matrix((0, 0))],
+                      format="csr")
+    q = np.concatenate([S.c - z / gamma, np.zeros(mi), lam[:me], lam[me:]])
+    h = np.concatenate([S.b[:me], np.zeros(mi)])
+    lo = np.concatenate([S.xl, S.b[me:], np.full(m, -np.inf)])
+    hi = np.concatenate([S.xu, np.full(mi, np.inf), np.full(m, np.inf)])
+    return InnerQP(n=n, m_e=me, m_i=mi, H=H, q=q, B=B, h=h, lo=lo, hi=hi)
+
+
+def warm_start(S: Scaled, x, lam, sigma):
+    """eq. (inner-warm-start): s = max{b_I, A_I x + lam_I / sigma_I},
+    r_E = A_E x - b_E, r_I = A_I x - s."""
+    me = S.m_e
+    ax = S.A @ x
+    s = np.maximum(S.b[me:], ax[me:] + lam[me:] / sigma[me:])
+    rE = ax[:me] - S.b[:me]
+    rI = ax[me:] - s
+    return np.concatenate([x, s, rE, rI])
+
+
+@dataclass
+class ScaledInner:
+    """Inner QP after penalty scaling and inner Ruiz scaling.
+
+    Scaled variables: w_hat = w / Sw, y_hat = y / Ey, where
+    Sw = Pw * F (Pw = 1 on x, s and 1/sqrt(sigma) on r: eq.
+    (inner-penalty-scaling)), and (Ey, F) are the inner Ruiz row/column
+    scales of B Pw.
+    """
+    H: sp.csr_matrix
+    q: np.ndarray
+    B: sp.csr_matrix
+    h: np.ndarray
+    lo: np.ndarray
+    hi: np.ndarray
+    Sw: np.ndarray
+    Ey: np.ndarray
+    m_w: np.ndarray
+    m_y: np.ndarray
+
+
+def scale_inner(qp: InnerQP, sigma, st: Settings):
+    """Penalty scaling (eq. (inner-penalty-scaling)) then inner Ruiz.
+
+    [reading] the inner Ruiz sweeps act on the penalty-scaled constraint
+    matrix B Pw only, like the outer scaling acts on the constraint matrix
+    only; its row and column scales are then applied to H, q, h and bounds.
+    """
+    n, mi = qp.n, qp.m_i
+    Pw = np.concatenate([np.ones(n + mi), 1.0 / np.sqrt(sigma)])
+    Bt = sp.csr_matrix(qp.B @ sp.diags(Pw))
+    Ey, F = ruiz(Bt, st.ruiz_sweeps)
+    Sw = Pw * F
+    Hs = sp.csr_matrix(sp.diags(Sw) @ qp.H @ sp.diags(Sw))
+    Bs = sp.csr_matrix(sp.diags(Ey) @ qp.B @ sp.diags(Sw))
+    m_w, m_y = diagonal_scales(Hs, Bs, sigma, n + mi)
+    return ScaledInner(H=Hs, q=Sw * qp.q, B=Bs, h=Ey * qp.h,
+                       lo=qp.lo / Sw, hi=qp.hi / Sw, Sw=Sw, Ey=Ey,
+                       m_w=m_w, m_y=m_y)
+
+
+def diagonal_scales(H, B, sigma, n_xs):
+    """eq. (diagonal-scales) on the scaled H and B.
+
+    m_w,i = ||H_:i||_1 + max{||B_:i||_1, (sum_j sigma_j B_ji^2)^(1/2)} for x
+    and s columns (the first ``n_xs``), + ||B_:i||_1 for r columns;
+    m_y,j = sum over i with m_w,i > 0 of B_ji^2 / m_w,i.
+    [reading] sigma_j is the raw (unscaled) row penalty.
+    """
+    h1 = np.asarray(abs(H).sum(axis=0)).ravel()
+    b1 = np.asarray(abs(B).sum(axis=0)).ravel()
+    B2 = B.multiply(B)
+    bs = np.sqrt(np.asarray(B2.T @ sigma).ravel()) if B.shape[0] else np.zeros_like(b1)
+    coup = b1.copy()
+    coup[:n_xs] = np.maximum(b1[:n_xs], bs[:n_xs])
+    m_w = h1 + coup
+    inv = np.where(m_w > 0, 1.0 / np.where(m_w > 0, m_w, 1.0), 0.0)
+    m_y = np.asarray(B2 @ inv).ravel()
+    return m_w, m_y
+
+
+def diagonal_steps(m_w, m_y, omega, st: Settings):
+    """eq. (diagonal-steps): tau = 0.99/(omega m_w), eta = 0.99 omega/m_y."""
+    tau = st.step_boost * 0.99 / (omega * m_w)
+    eta = st.step_boost * 0.99 * omega / m_y
+    return tau, eta
+
+
+# ---------------------------------------------------------------------------
+# Inner solver (Algorithm "practical diagonal PDHG")
+# ---------------------------------------------------------------------------
+
+def trial_step(si: ScaledInner, w, wbar, y, tau, eta, alpha, beta):
+    """eq. (pdqp-trial): primal step at the middle-point gradient with box
+    projection, then dual step with extrapolation."""
+    grad = si.q + (1.0 - alpha) * (si.H @ wbar) + alpha * (si.H @ w) - si.B.T @ y
+    w_tr = np.clip(w - tau * grad, si.lo, si.hi)
+    Bw_tr = si.B @ w_tr
+    y_tr = y + eta * (si.h - Bw_tr - beta * (Bw_tr - si.B @ w))
+    return w_tr, y_tr
+
+
+def adaptive_condition(si: ScaledInner, dw, dy, tau, eta):
+    """eq. (adaptive-condition): returns (lhs, rhs); accepted iff lhs >= rhs."""
+    lhs = 0.5 * float(np.sum(dw * dw / tau)) + 0.5 * float(np.sum(dy * dy / eta))
+    rhs = 0.5 * float(np.sum(np.abs(dw * (si.H @ dw)))) + \
+        float(np.sum(np.abs(dw * (si.B.T @ dy))))
+    return lhs, rhs
+
+
+def _ninf(v):
+    return float(np.max(np.abs(v))) if v.size else 0.0
+
+
+def inner_residuals(qp: InnerQP, w, y):
+    """eq. (inner-residuals) and (inner-scales) on the (penalty- and
+    Ruiz-unscaled) inner QP.  [reading] evaluated in the coordinates of
+    (inner-qp) itself."""
+    Bw = qp.B @ w
+    Hw = qp.H @ w
+    Bty = qp.B.T @ y
+    g = Hw + qp.q - Bty
+    rp = _ninf(Bw - qp.h)
+    rd = _ninf(w - np.clip(w - g, qp.lo, qp.hi))
+    sp_ = max(1.0, _ninf(Bw), _ninf(qp.h))
+    sd = max(1.0, _ninf(Hw), _ninf(qp.q), _ninf(Bty))
+    return rp, rd, sp_, sd
+
+
+def restart_metric_parts(si: ScaledInner, w, y):
+    """[reading] Squared primal and dual residual norms in scaled
+    coordinates: ||h - Bw||^2 and ||w - P(w - (Hw + q - B'y))||^2.  The
+    restart metric is KKT_omega = sqrt(omega^2 P + D / omega^2)."""
+    pr = si.h - si.B @ w
+    g = si.H @ w + si.q - si.B.T @ y
+    dr = w - np.clip(w - g, si.lo, si.hi)
+    return float(pr @ pr), float(dr @ dr)
+
+
+def kkt_omega(parts, omega):
+    p, d = parts
+    return math.sqrt(omega * omega * p + d / (omega * omega))
+
+
+@dataclass
+class Trace:
+    """Per-iteration record for parity checks: unscaled inner (w, y) after
+    each accepted trial (first ``max_iters``), every trial's (lhs, rhs,
+    accepted), and every check's outcome."""
+    max_iters: int = 0
+    w: list = field(default_factory=list)
+    y: list = field(default_factory=list)
+    trials: list = field(default_factory=list)
+    checks: list = field(default_factory=list)
+    outer: list = field(default_factory=list)
+
+
+@dataclass
+class InnerState:
+    qp: InnerQP
+    si: ScaledInner
+    w: np.ndarray            # scaled current primal
+    y: np.ndarray            # scaled current dual
+    wbar: np.ndarray
+    ybar: np.ndarray
+    tau: np.ndarray
+    eta: np.ndarray
+    N: int = 0               # accepted trials in this restart epoch
+    t: int = 0               # accepted trials since this inner QP was formed
+    w_anchor: np.ndarray = None
+    y_anchor: np.ndarray = None
+    kkt_anchor: float = math.inf
+    kkt_prev: float = math.inf
+
+
+def new_inner_state(qp, si, w0, y0, omega, st):
+    w = w0 / si.Sw
+    y = y0 / si.Ey
+    tau, eta = diagonal_steps(si.m_w, si.m_y, omega, st)
+    s = InnerState(qp=qp, si=si, w=w, y=y, wbar=w.copy(), ybar=y.copy(),
+                   tau=tau, eta=eta, w_anchor=w.copy(), y_anchor=y.copy())
+    s.kkt_anchor = kkt_omega(restart_metric_parts(si, w, y), omega)
+    return s
+
+
+@dataclass
+class Counters:
+    trials: int = 0
+    accepted: int = 0
+    rejected: int = 0
+    restarts: int = 0
+
+
+def inner_solve(state: InnerState, omega, delta_a, delta_r, st: Settings,
+                cnt: Counters, trace: Trace = None, deadline=math.inf):
+    """Algorithm "practical diagonal PDHG" from an already formed state.
+
+    Returns (status, omega).  On INNER_CONVERGED the state's (w, y) is the
+    candidate that passed.  [reading] N_p = N_d = N (accepted trials in the
+    epoch); averaging weight alpha (the middle-point weight); checks after
+    every ``check_every`` accepted trials since the QP was formed and at the
+    per-call limit; the current candidate is tested before the average.
+    """
+    si, qp = state.si, state.qp
+    t_call = 0
+    rejects = 0
+    while True:
+        alpha = 2.0 / (state.N + 2.0)
+        beta = state.N / (state.N + 1.0)
+        w_tr, y_tr = trial_step(si, state.w, state.wbar, state.y,
+                                state.tau, state.eta, alpha, beta)
+        dw = w_tr - state.w
+        dy = y_tr - state.y
+        lhs, rhs = adaptive_condition(si, dw, dy, state.tau, state.eta)
+        cnt.trials += 1
+        if not (math.isfinite(lhs) and math.isfinite(rhs)):
+            return INNER_NUMERICAL_ERROR, omega
+        accepted = lhs >= rhs
+        if trace is not None:
+            trace.trials.append((lhs, rhs, bool(accepted)))
+        if not accepted:
+            # [reading] common shrink of primal and dual steps
+            kappa = min(max(st.shrink_safety * lhs / rhs, st.shrink_min), st.shrink_max)
+            state.tau = kappa * state.tau
+            state.eta = kappa * state.eta
+            rejects += 1
+            cnt.rejected += 1
+            if rejects >= st.max_rejects:
+                return INNER_NUMERICAL_ERROR, omega
+            continue
+        rejects = 0
+        state.wbar = (1.0 - alpha) * state.wbar + alpha * w_tr
+        state.ybar = (1.0 - alpha) * state.ybar + alpha * y_tr
+        state.w, state.y = w_tr, y_tr
+        state.N += 1
+        state.t += 1
+        t_call += 1
+        cnt.accepted += 1
+        if trace is not None and len(trace.w) < trace.max_iters:
+            trace.w.append(si.Sw * state.w)
+            trace.y.append(si.Ey * state.y)
+
+        at_limit = t_call >= st.max_inner
+        if state.t % st.check_every != 0 and not at_limit:
+            continue
+        # --- stopping check: current first, then average
+        for which, (wc, yc) in enumerate(((state.w, state.y), (state.wbar, state.ybar))):
+            rp, rd, sp_, sd = inner_residuals(qp, si.Sw * wc, si.Ey * yc)
+            if rp <= delta_a + delta_r * sp_ and rd <= delta_a + delta_r * sd:
+                if which == 1:
+                    state.w, state.y = state.wbar.copy(), state.ybar.copy()
+                if trace is not None:
+                    trace.checks.append(("converged", state.t, which))
+                return INNER_CONVERGED, omega
+        # --- restart check
+        parts_c = restart_metric_parts(si, state.w, state.y)
+        parts_a = restart_metric_parts(si, state.wbar, state.ybar)
+        k_c = kkt_omega(parts_c, omega)
+        k_a = kkt_omega(parts_a, omega)
+        use_avg = k_a < k_c
+        k_cand = k_a if use_avg else k_c
+        restart = (k_cand <= st.restart_suff * state.kkt_anchor or
+                   (k_cand <= st.restart_nec * state.kkt_anchor and k_cand > state.kkt_prev) or
+                   state.N >= st.restart_art * state.t)
+        if trace is not None:
+            trace.checks.append(("restart" if restart else "continue", state.t, int(use_avg)))
+        if restart:
+            if use_avg:
+                state.w, state.y = state.wbar.copy(), state.ybar.copy()
+                parts = parts_a
+            else:
+                parts = parts_c
+            dW = float(np.linalg.norm(state.w - state.w_anchor))
+            dY = float(np.linalg.norm(state.y - state.y_anchor))
+            if dW > 0 and dY > 0:
+                # eq. (primal-weight-update)
+                omega = math.exp(0.25 * math.log(dY / dW) + 0.75 * math.log(omega))
+            state.tau, state.eta = diagonal_steps(si.m_w, si.m_y, omega, st)
+            state.wbar, state.ybar = state.w.copy(), state.y.copy()
+            state.N = 0
+            state.w_anchor, state.y_anchor = state.w.copy(), state.y.copy()
+            state.kkt_anchor = kkt_omega(parts, omega)
+            state.kkt_prev = math.inf
+            cnt.restarts += 1
+        else:
+            state.kkt_prev = k_cand
+        if at_limit:
+            return INNER_ITER_LIMIT, omega
+        if time.monotonic() > deadline:
+            return INNER_TIME_LIMIT, omega
+
+
+# ---------------------------------------------------------------------------
+# Outer loop (Algorithm "practical outer iteration")
+# ---------------------------------------------------------------------------
+
+def multiplier_update(S: Scaled, x, lam, sigma):
+    """eq. (practical-multiplier-update): s_I = max{b_I, A_I x + lam_I / sigma_I},
+    lam_E += sigma_E (A_E x - b_E), lam_I = min{0, lam_I + sigma_I (A_I x - b_I)}.
+    Returns (A x, s_I, new lambda)."""
+    me = S.m_e
+    ax = S.A @ x
+    s_new = np.maximum(S.b[me:], ax[me:] + lam[me:] / sigma[me:])
+    lam_new = lam.copy()
+    lam_new[:me] = lam[:me] + sigma[:me] * (ax[:me] - S.b[:me])
+    lam_new[me:] = np.minimum(0.0, lam[me:] + sigma[me:] * (ax[me:] - S.b[me:]))
+    return ax, s_new, lam_new
+
+
+def outer_residuals(S: Scaled, x, lam):
+    """eq. (outer-residuals) and (outer-scales) on the scaled data."""
+    me = S.m_e
+    ax = S.A @ x
+    qx = S.Q @ x
+    atl = S.A.T @ lam
+    rp = max(_ninf(ax[:me] - S.b[:me]), _ninf(np.maximum(S.b[me:] - ax[me:], 0.0)))
+    rd = _ninf(x - np.clip(x - qx - S.c - atl, S.xl, S.xu))
+    sp_ = max(1.0, _ninf(ax[:me]), _ninf(S.b[:me]), _ninf(ax[me:]), _ninf(S.b[me:]))
+    sd = max(1.0, _ninf(qx), _ninf(S.c), _ninf(atl))
+    return rp, rd, sp_, sd
+
+
+@dataclass
+class Result:
+    status: int
+    x: np.ndarray
+    lam: np.ndarray
+    outer_iters: int
+    counters: Counters
+    gamma: float
+    lambda_hat: float
+    r_p: float = math.nan
+    r_d: float = math.nan
+    s_p: float = math.nan
+    s_d: float = math.nan
+    objective: float = math.nan
+    scaled_x: np.ndarray = None
+    scaled_lam: np.ndarray = None
+    sigma: np.ndarray = None
+    omega: float = math.nan
+
+
+def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
+    """Full method: outer scaling, gamma, initial penalties, then the
+    practical outer iteration with the practical inner solver."""
+    st = st or Settings()
+    t_start = time.monotonic()
+    deadline = t_start + st.time_limit
+    P = normalise(prob)
+    n, me, mi = P.n, P.m_e, P.m_i
+    m = me + mi
+    x0 = np.zeros(n) if x0 is None else np.asarray(x0, float)
+    x0 = np.clip(x0, P.xl, P.xu)
+    S = outer_scale(P, x0, st.ruiz_sweeps, st.outer_scaling)
+    # initial outer duals in internal rows, with lambda_I <= 0
+    if lam0 is None:
+        lam_int = np.zeros(m)
+    else:
+        lam_int = P.sign_of * np.asarray(lam0, float)[P.row_of]
+        lam_int[me:] = np.minimum(lam_int[me:], 0.0)
+    gamma, lam_hat = choose_gamma(S.Q, st)
+    x = x0 / S.Dx
+    z = x.copy()
+    lam = S.c_obj * lam_int / S.Dc
+    sigma = initial_penalty(S, x, st)
+    delta_a = delta_r = eps_ak = eps_rk = 1.0
+    omega = st.omega0
+    y = -lam.copy()               # [reading] inner dual starts at -lambda
+    r_prev = None
+    cnt = Counters()
+    state = None
+    status = MAX_ITER
+    k = 0
+    rp = rd = sp_ = sd = math.nan
+    while k < st.max_outer:
+        if state is None:
+            qp = form_inner_qp(S, z, lam, sigma, gamma)
+            si = scale_inner(qp, sigma, st)
+            w0 = warm_start(S, x, lam, sigma)
+            state = new_inner_state(qp, si, w0, y, omega, st)
+        ist, omega = inner_solve(state, omega, delta_a, delta_r, st, cnt, trace, deadline)
+        k += 1
+        x_in = (state.si.Sw * state.w)[:n]
+        y = state.si.Ey * state.y
+        if ist == INNER_NUMERICAL_ERROR:
+            status = NUMERICAL_ERROR
+            x = x_in
+            break
+        if ist == INNER_TIME_LIMIT:
+            status = TIME_LIMIT
+            x = x_in
+            break
+        if ist == INNER_ITER_LIMIT:
+            x = x_in
+            if time.monotonic() > deadline:
+                status = TIME_LIMIT
+                break
+            continue
+        x_new = x_in
+        ax, s_new, lam = multiplier_update(S, x_new, lam, sigma)
+        rp, rd, sp_, sd = outer_residuals(S, x_new, lam)
+        if trace is not None:
+            trace.outer.append((k, rp, rd, sp_, sd))
+        if rp <= st.eps_abs + st.eps_rel * sp_ and rd <= st.eps_abs + st.eps_rel * sd:
+            x = x_new
+            status = SOLVED
+            break
+        # row-wise penalty update, eq. (penalty-trigger-eq)
+        r_row = np.concatenate([ax[:me] - S.b[:me], ax[me:] - s_new])
+        if r_prev is not None:
+            rn = _ninf(r_row)
+            active = np.concatenate([np.ones(me, bool), lam[me:] < 0.0])
+            trig = (np.abs(r_row) > st.theta_sigma * np.abs(r_prev)) & active
+            if st.penalty_gate:
+                trig &= np.abs(r_row) > st.eps_abs + st.eps_rel * sp_
+            if rn > 0:
+                fac = np.maximum(1.0, st.sigma_growth * np.abs(r_row) / rn)
+                sigma = np.where(trig, np.minimum(st.sigma_max, sigma * fac), sigma)
+        r_prev = r_row
+        # eq. (inner-tolerance-factor); [reading] ratio 1 when r_d = 0,
+        # tolerances floored at the outer tolerances
+        dxz = _ninf(x_new - z)
+        ratio = 1.0 if rd == 0 else min(1.0, dxz / gamma / rd)
+        rho = st.rho_in_max - (st.rho_in_max - st.rho_in_min) * ratio
+        delta_a = max(st.eps_abs, rho * delta_a)
+        delta_r = max(st.eps_rel, rho * delta_r)
+        # eq. (center-update) / (center-tolerance-update)
+        if rp <= eps_ak + eps_rk * sp_:
+            z = x_new.copy()
+            eps_ak *= st.rho_z
+            eps_rk *= st.rho_z
+        x = x_new
+        state = None
+        if time.monotonic() > deadline:
+            status = TIME_LIMIT
+            break
+    # unscale (Section 3.1) and map back to the caller's rows
+    x_orig = S.Dx * x
+    lam_scaled_int = lam
+    lam_int_orig = S.Dc * lam / S.c_obj
+    lam_out = np.zeros(prob["A"].shape[0])
+    np.add.at(lam_out, P.row_of, P.sign_of * lam_int_orig)
+    res = Result(status=status, x=x_orig, lam=lam_out, outer_iters=k, counters=cnt,
+                 gamma=gamma, lambda_hat=lam_hat, scaled_x=x, scaled_lam=lam_scaled_int,
+                 sigma=sigma, omega=omega)
+    res.r_p, res.r_d, res.s_p, res.s_d = external_kkt(prob, x_orig, lam_out)
+    Qo = sp.csr_matrix(prob["Q"])
+    res.objective = 0.5 * float(x_orig @ (Qo @ x_orig)) + float(np.asarray(prob["c"]) @ x_orig)
+    return res
+
+
+def external_kkt(prob, x, lam):
+    """KKT test on the original (unscaled) problem, as in the paper's
+    experimental protocol: primal residual includes variable-bound
+    violation; projected stationarity; scales as in (outer-scales).
+    ``lam`` is indexed by the caller's rows (rl <= a'x <= ru convention:
+    lam <= 0 at a lower row bound, >= 0 at an upper one)."""
+    A = sp.csr_matrix(prob["A"])
+    Q = sp.csr_matrix(prob["Q"])
+    c = np.asarray(prob["c"], float)
+    rl = np.asarray(prob["rl"], float)
+    ru = np.asarray(prob["ru"], float)
+    xl = np.asarray(prob["xl"], float)
+    xu = np.asarray(prob["xu"], float)
+    ax = A @ x
+    viol = np.maximum(np.maximum(rl - ax, ax - ru), 0.0)
+    rp = max(_ninf(viol), _ninf(np.maximum(xl - x, 0.0)), _ninf(np.maximum(x - xu, 0.0)))
+    qx = Q @ x
+    atl = A.T @ lam
+    rd = _ninf(x - np.clip(x - qx - c - atl, xl, xu))
+    fin = lambda v: v[np.isfinite(v)]
+    sp_ = max(1.0, _ninf(ax), _ninf(fin(rl)), _ninf(fin(ru)))
+    sd = max(1.0, _ninf(qx), _ninf(c), _ninf(atl))
+    return rp, rd, sp_, sd
+
+
+def passes_external(res: Result, eps_abs, eps_rel):
+    return (res.r_p <= eps_abs + eps_rel * res.s_p and
+            res.r_d <= eps_abs + eps_rel * res.s_d)
