@@ -1,0 +1,238 @@
+/*
+ * pdnqp.h -- C ABI of the MI355X (gfx950) PDNQP hot path.
+ *
+ * PDNQP finds stationary (KKT) points of sparse, possibly nonconvex QPs
+ *
+ *     min 1/2 x'Qx + c'x   s.t.  rl <= A x <= ru,   xl <= x <= xu
+ *
+ * (paper: Section 2, problem (qp) and stationarity (kkt-stationarity)) by a
+ * proximal augmented-Lagrangian outer loop (Algorithm "practical outer
+ * iteration", Section 3.2) whose strongly convex residual-form subproblems
+ * (eq. (inner-qp)) are solved by a diagonal, adaptive, restarted accelerated
+ * PDHG (Algorithm "practical diagonal PDHG", Section 3.3).  Every iteration
+ * of both loops runs as HIP kernels on one GPU; the host only issues
+ * launches and reads back a few scalars per check.
+ *
+ * Conventions for every function below:
+ *  - Functions returning int return PDNQP_OK (0) on success and a negative
+ *    PDNQP_E_* code on error; they never throw and never abort.  After an
+ *    error, pdnqp_last_error() describes it.
+ *  - All array arguments are HOST pointers, read (or written) only during
+ *    the call; the library copies what it keeps.  Sizes are element counts.
+ *  - Sparse matrices are CSR with int32 row pointers (length rows+1,
+ *    starting at 0, nondecreasing) and int32 column indices (sorted
+ *    strictly increasing within each row, in range), FP64 values.
+ *  - A solver handle is not thread-safe; distinct handles may be used from
+ *    distinct threads concurrently (each owns its HIP stream).
+ */
+#ifndef PDNQP_H
+#define PDNQP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes (return values). */
+enum {
+  PDNQP_OK = 0,
+  PDNQP_E_INVALID = -1, /* bad argument: shape, index, ordering, symmetry, non-finite data, bounds */
+  PDNQP_E_NOMEM = -2,   /* device or host allocation failed */
+  PDNQP_E_DEVICE = -3,  /* a HIP runtime call failed */
+  PDNQP_E_STATE = -4    /* operation not valid for this handle (e.g. no trace recorded) */
+};
+
+/* Solver outcomes (pdnqp_info.status).  Algorithm "practical outer
+ * iteration": termination (outer-termination), iteration limit, and the
+ * inner solver's numerical-error exit (rejection limit). */
+enum {
+  PDNQP_SOLVED = 1,
+  PDNQP_MAX_ITER = 2,
+  PDNQP_TIME_LIMIT = 3,
+  PDNQP_NUMERICAL_ERROR = 4
+};
+
+/* Outer scaling modes (Section 3.1, eq. (scaled-problem)). */
+enum {
+  PDNQP_SCALE_RUIZ_A = 0,  /* Ruiz sweeps on the combined constraint matrix [A_E; A_I] (the paper's) */
+  PDNQP_SCALE_NONE = 1,    /* no outer scaling (D_c = D_x = 1; the objective scalar still applies) */
+  PDNQP_SCALE_RUIZ_QA = 2  /* Ruiz sweeps where a column's norm also counts the symmetric Q */
+};
+
+/* Solver parameters.  Obtain defaults with pdnqp_default_settings() and
+ * override fields.  Fields marked [paper] take the defaults of the paper's
+ * parameter table; fields marked [reading] fix points the paper leaves
+ * open (each documented where it is used). */
+typedef struct pdnqp_settings {
+  int64_t max_outer;       /* [paper] outer iteration limit K_out, 2^31-1 */
+  int32_t max_inner;       /* [paper] accepted inner iterations per outer call K_in, 40000 */
+  int32_t ruiz_sweeps;     /* [paper] outer and inner Ruiz sweeps, 8 */
+  double time_limit_s;     /* [paper] wall-clock limit, +inf */
+  double sigma_init;       /* [paper] initial row-penalty scale, 20 */
+  double theta_sigma;      /* [paper] residual-reduction threshold of the penalty update, 0.25 */
+  double delta_gamma;      /* [paper] margin of the proximal step (R-choice), 1e-2 */
+  double rho_in_min;       /* [paper] fast inner-tolerance factor, 0.3 */
+  double rho_in_max;       /* [paper] slow inner-tolerance factor, 0.95 */
+  double rho_z;            /* [paper] centre-tolerance factor, 0.95 */
+  int32_t check_every;     /* [reading] accepted trials between inner stopping/restart checks, 64 */
+  int32_t max_rejects;     /* [reading] consecutive rejected trials => numerical error, 50 */
+  double restart_suff;     /* [reading] sufficient KKT decay for a restart, 0.2 */
+  double restart_nec;      /* [reading] necessary KKT decay (with no progress), 0.8 */
+  double restart_art;      /* [reading] artificial restart: epoch >= this * inner count, 0.36 */
+  double shrink_safety;    /* [reading] rejected-trial step factor clamp(safety*L/R, min, max): 0.95 */
+  double shrink_min;       /*   0.1 */
+  double shrink_max;       /*   0.9 */
+  double omega0;           /* [reading] initial primal weight, 1 */
+  double sigma_growth;     /* [reading] penalty growth multiplier, 10 */
+  double sigma_max;        /* [reading] penalty cap, 1e9 */
+  double sigma0_min;       /* [reading] clamp of the initial penalty, 1e-4 */
+  double sigma0_max;       /*   1e4 */
+  int32_t penalty_gate;    /* [reading] rows already within the outer tolerance are not penalised further, 1 */
+  int32_t lanczos_iters;   /* [reading] Lanczos steps for the smallest eigenvalue of Q, 100 */
+  double gamma_override;   /* > 0: use this proximal step instead of the Lanczos rule; 0 (default) */
+  double step_boost;       /* multiplies the diagonal steps at every rebuild; 1 (testing knob) */
+  int32_t outer_scaling;   /* PDNQP_SCALE_*, default PDNQP_SCALE_RUIZ_A */
+  int32_t profile;         /* 1: time the per-trial kernels with HIP events (pdnqp_kernel_stats) */
+  int32_t trace_iters;     /* record unscaled inner (w, y) after each of the first N accepted trials */
+  int32_t trace_trials;    /* record (L, R, accepted) of the first N trials and the first N checks */
+  void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
+  /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
+   * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */
+  void *(*dev_alloc)(size_t bytes, void *user);
+  void (*dev_free)(void *ptr, void *user);
+  void *alloc_user;
+} pdnqp_settings;
+
+/* Per-solve report. */
+typedef struct pdnqp_info {
+  int32_t status;          /* PDNQP_SOLVED ... */
+  int32_t reserved;
+  int64_t outer_iters;     /* outer iterations performed */
+  int64_t inner_trials;    /* trial steps (accepted + rejected) */
+  int64_t inner_accepted;  /* accepted inner iterations */
+  int64_t inner_rejected;
+  int64_t restarts;
+  int64_t checks;
+  /* Final KKT test on the ORIGINAL (unscaled) problem: primal residual
+   * including bound violation, projected stationarity, and their scales
+   * (outer-residuals)/(outer-scales) evaluated on the caller's data. */
+  double r_p, r_d, s_p, s_d;
+  /* The same four quantities on the scaled problem at the last outer step
+   * (what the termination test used). */
+  double r_p_scaled, r_d_scaled, s_p_scaled, s_d_scaled;
+  double objective;        /* 1/2 x'Qx + c'x at the returned x */
+  double gamma;            /* proximal step used (scaled problem) */
+  double lambda_hat;       /* Lanczos estimate of the smallest eigenvalue of the scaled Q */
+  double omega;            /* final primal weight */
+  double setup_s;          /* seconds in scaling/Lanczos/penalty set-up inside pdnqp_solve */
+  double solve_s;          /* seconds of the whole pdnqp_solve call */
+} pdnqp_info;
+
+/* Writes the defaults into *s.  Never fails. */
+void pdnqp_default_settings(pdnqp_settings *s);
+
+/* Size in bytes of pdnqp_settings / pdnqp_info as compiled into the library
+ * (lets bindings check their struct layout). */
+size_t pdnqp_settings_size(void);
+size_t pdnqp_info_size(void);
+
+typedef struct pdnqp_solver pdnqp_solver;
+
+/* Creates a solver for one QP and uploads it to the current HIP device.
+ *  n >= 1 variables, m >= 0 rows.
+ *  Q:   n x n CSR (Qp, Qi, Qx), symmetric with both triangles stored.
+ *  A:   m x n CSR (Ap, Ai, Ax).
+ *  c, xl, xu: length n; xl <= xu, xl may be -INFINITY, xu +INFINITY.
+ *  rl, ru:    length m; rl <= ru.  rl == ru is an equality row; a row with
+ *             only rl finite is A_I x >= rl; only ru finite is negated into
+ *             that form; both finite is split into two such rows; both
+ *             infinite is ignored.
+ *  settings:  NULL for defaults.  Copied.
+ * On success *out owns all device memory it allocated (released by
+ * pdnqp_destroy).  On error *out is NULL.  Errors: PDNQP_E_INVALID for any
+ * malformed input (checked before any device call), PDNQP_E_NOMEM,
+ * PDNQP_E_DEVICE. */
+int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m,
+                 const int32_t *Qp, const int32_t *Qi, const double *Qx,
+                 const int32_t *Ap, const int32_t *Ai, const double *Ax,
+                 const double *c, const double *xl, const double *xu,
+                 const double *rl, const double *ru,
+                 const pdnqp_settings *settings);
+
+/* Solves to  r_p <= eps_abs + eps_rel*s_p  and  r_d <= eps_abs + eps_rel*s_d
+ * (outer-termination) on the scaled problem.
+ *  x0 (length n) and lambda0 (length m, caller's rows) are optional warm
+ *  starts (NULL: zero); x0 is clipped into [xl, xu].
+ *  x_out (length n), lambda_out (length m): caller-owned host buffers,
+ *  written on PDNQP_OK whatever the solver outcome; lambda follows the
+ *  sign convention  Qx + c + A'lambda + N_[xl,xu](x) contains 0, i.e.
+ *  lambda <= 0 on a row at its lower bound and >= 0 at its upper bound.
+ *  info: optional (NULL allowed).
+ * The call blocks until the solve ends (it synchronises its stream). */
+int pdnqp_solve(pdnqp_solver *s, double eps_abs, double eps_rel,
+                const double *x0, const double *lambda0,
+                double *x_out, double *lambda_out, pdnqp_info *info);
+
+/* Solves `count` independent QPs (each with its own handle, all created on
+ * the same device) from zero starts, writing x_out[i], lambda_out[i] and
+ * infos[i] (infos may be NULL).  Returns the first error encountered; a
+ * solver outcome other than PDNQP_SOLVED is not an error. */
+int pdnqp_solve_batch(int32_t count, pdnqp_solver *const *solvers,
+                      double eps_abs, double eps_rel,
+                      double *const *x_out, double *const *lambda_out,
+                      pdnqp_info *infos);
+
+/* Releases the handle and its device memory.  NULL is a no-op. */
+void pdnqp_destroy(pdnqp_solver *s);
+
+/* Message of the last error on this thread ("" if none).  Valid until the
+ * next library call on this thread. */
+const char *pdnqp_last_error(void);
+
+/* Internal dimensions after row normalisation: number of equality rows,
+ * inequality rows (after splitting two-sided rows) and the inner primal
+ * length d_w = n + m_I + m_E + m_I.  Any pointer may be NULL. */
+int pdnqp_dims(const pdnqp_solver *s, int32_t *m_e, int32_t *m_i, int32_t *d_w);
+
+/* Copies out what the last pdnqp_solve recorded when trace_iters /
+ * trace_trials were set:
+ *  iters:  number of recorded accepted iterations (<= trace_iters);
+ *  w, y:   if non-NULL, iters*d_w and iters*(m_e+m_i) doubles: the inner
+ *          iterate (x, s_I, r_E, r_I) and inner dual (y_E, y_I) after each
+ *          accepted trial, in the outer-scaled, penalty- and Ruiz-unscaled
+ *          coordinates of (inner-qp), internal row order (equalities first);
+ *  trials: number of recorded trials; tr (if non-NULL) gets 3 doubles per
+ *          trial: lhs and rhs of (adaptive-condition) and 1.0/0.0 accepted;
+ *  checks: number of recorded checks; ck (if non-NULL) gets 4 int32 per
+ *          check: kind (0 continue, 1 restart, 2 converged), accepted
+ *          count t at the check, candidate (0 current, 1 average), and the
+ *          number of trials of the solve so far.
+ * Pass NULL buffers first to query counts.  PDNQP_E_STATE if nothing was
+ * recorded. */
+int pdnqp_get_trace(const pdnqp_solver *s, int32_t *iters, double *w, double *y,
+                    int32_t *trials, double *tr, int32_t *checks, int32_t *ck);
+
+/* Per-kernel timings gathered when settings.profile = 1 during the last
+ * pdnqp_solve: for each kernel class, the launch count, summed and average
+ * duration (HIP events on the solver's stream) and the kernel's algorithmic
+ * bytes per launch (matrix values and indices once, every vector it reads
+ * or writes once).  Writes up to `cap` entries; *count receives the number
+ * available. */
+typedef struct pdnqp_kernel_stat {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double avg_us;
+  double bytes_per_launch;
+} pdnqp_kernel_stat;
+
+int pdnqp_kernel_stats(const pdnqp_solver *s, pdnqp_kernel_stat *out, int32_t cap,
+                       int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDNQP_H */

@@ -449,6 +449,10 @@ def adaptive_condition(si: ScaledInner, dw, dy, tau, eta):
     return lhs, rhs
 
 
+def _ratio(a, b):
+    return a / b if b > 0 else (math.inf if a > 0 else 0.0)
+
+
 def _ninf(v):
     return float(np.max(np.abs(v))) if v.size else 0.0
 
@@ -487,7 +491,10 @@ def kkt_omega(parts, omega):
 class Trace:
     """Per-iteration record for parity checks: unscaled inner (w, y) after
     each accepted trial (first ``max_iters``), every trial's (lhs, rhs,
-    accepted), and every check's outcome."""
+    accepted), and every check's outcome as (kind, accepted count t,
+    candidate, trials so far, termination ratio), the ratio being the
+    smaller over the two candidates of max(r_p / tol_p, r_d / tol_d) (<= 1
+    passes)."""
     max_iters: int = 0
     w: list = field(default_factory=list)
     y: list = field(default_factory=list)
@@ -585,13 +592,16 @@ def inner_solve(state: InnerState, omega, delta_a, delta_r, st: Settings,
         if state.t % st.check_every != 0 and not at_limit:
             continue
         # --- stopping check: current first, then average
+        ratio = math.inf
         for which, (wc, yc) in enumerate(((state.w, state.y), (state.wbar, state.ybar))):
             rp, rd, sp_, sd = inner_residuals(qp, si.Sw * wc, si.Ey * yc)
+            ratio = min(ratio, max(_ratio(rp, delta_a + delta_r * sp_),
+                                   _ratio(rd, delta_a + delta_r * sd)))
             if rp <= delta_a + delta_r * sp_ and rd <= delta_a + delta_r * sd:
                 if which == 1:
                     state.w, state.y = state.wbar.copy(), state.ybar.copy()
                 if trace is not None:
-                    trace.checks.append(("converged", state.t, which))
+                    trace.checks.append(("converged", state.t, which, cnt.trials, ratio))
                 return INNER_CONVERGED, omega
         # --- restart check
         parts_c = restart_metric_parts(si, state.w, state.y)
@@ -604,7 +614,8 @@ def inner_solve(state: InnerState, omega, delta_a, delta_r, st: Settings,
                    (k_cand <= st.restart_nec * state.kkt_anchor and k_cand > state.kkt_prev) or
                    state.N >= st.restart_art * state.t)
         if trace is not None:
-            trace.checks.append(("restart" if restart else "continue", state.t, int(use_avg)))
+            trace.checks.append(("restart" if restart else "continue", state.t, int(use_avg),
+                                 cnt.trials, ratio))
         if restart:
             if use_avg:
                 state.w, state.y = state.wbar.copy(), state.ybar.copy()

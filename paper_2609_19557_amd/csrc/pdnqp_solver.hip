@@ -1,0 +1,713 @@
+// Host driver of the gfx950 PDNQP solver (see pdnqp_solver.hpp).
+//
+// Per outer step (Algorithm "practical outer iteration"): form the inner QP
+// on the device (warm start, penalty + inner Ruiz scaling folded into the
+// step vectors, diagonal steps), run the inner PDHG in chunks of trial
+// slots whose accept/reject/restart decisions are taken on the device, read
+// back the control block once per chunk, then update multipliers, residuals,
+// penalties, tolerances and the proximal centre.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <limits>
+
+#include "pdnqp_solver.hpp"
+
+namespace pdnqp {
+
+namespace {
+
+double now_s() {
+  using clk = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+int pick_G(int64_t nnz, int32_t rows) {
+  const double avg = rows > 0 ? (double)nnz / rows : 1.0;
+  int G = 2;
+  while (G < avg && G < 32) G *= 2;
+  return G;
+}
+
+// Smallest eigenvalue of the symmetric tridiagonal matrix (a, b) by
+// bisection on Sturm-sequence counts (Gershgorin starting interval).
+double tridiag_min_eig(const std::vector<double> &a, const std::vector<double> &b) {
+  const int k = (int)a.size();
+  double lo = std::numeric_limits<double>::infinity(), hi = -lo, bmax2 = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < k - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+    if (i < k - 1) bmax2 = std::max(bmax2, b[i] * b[i]);
+  }
+  const double pivmin = std::numeric_limits<double>::min() * std::max(1.0, bmax2);
+  auto count_below = [&](double x) {
+    int cnt = 0;
+    double d = a[0] - x;
+    if (std::fabs(d) < pivmin) d = -pivmin;
+    if (d < 0) ++cnt;
+    for (int i = 1; i < k; ++i) {
+      d = a[i] - x - b[i - 1] * b[i - 1] / d;
+      if (std::fabs(d) < pivmin) d = -pivmin;
+      if (d < 0) ++cnt;
+    }
+    return cnt;
+  };
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= 2.0 * eps * std::max(std::fabs(lo), std::fabs(hi)) + pivmin) break;
+    if (mid <= lo || mid >= hi) break;
+    if (count_below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double ninf(const std::vector<double> &v) {
+  double m = 0.0;
+  for (double x : v) m = std::max(m, std::fabs(x));
+  return m;
+}
+
+enum TimerId { TM_XTRIAL = 0, TM_QA = 1, TM_AT = 2, TM_COUNT = 3 };
+
+}  // namespace
+
+Solver::~Solver() {
+  if (stream_) hipStreamSynchronize(stream_);
+  for (auto &t : timers_)
+    for (auto e : t.ev) hipEventDestroy(e);
+  for (void *p : allocs_) dfree(p);
+  if (hctrl_) hipHostFree(hctrl_);
+  if (own_stream_ && stream_) hipStreamDestroy(stream_);
+}
+
+void *Solver::dalloc(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~size_t(255);
+  void *p = nullptr;
+  if (st_.dev_alloc) {
+    p = st_.dev_alloc(bytes, st_.alloc_user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) allocs_.push_back(p);
+  return p;
+}
+
+void Solver::dfree(void *p) {
+  if (!p) return;
+  if (st_.dev_free) st_.dev_free(p, st_.alloc_user);
+  else hipFree(p);
+}
+
+int Solver::check(hipError_t e, const char *what, std::string &err) {
+  if (e == hipSuccess) return PDNQP_OK;
+  err = std::string(what) + ": " + hipGetErrorString(e);
+  return PDNQP_E_DEVICE;
+}
+
+int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
+  qp_ = std::move(qp);
+  st_ = st;
+  const int32_t n = qp_.n, m = qp_.m, mi = qp_.mi;
+  const int64_t nzq = qp_.Qi.size(), nza = qp_.Ai.size();
+  if (st_.hip_stream) {
+    stream_ = (hipStream_t)st_.hip_stream;
+  } else {
+    int r = check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate", err);
+    if (r) return r;
+    own_stream_ = true;
+  }
+  int r = check(hipHostMalloc((void **)&hctrl_, sizeof(Ctrl), hipHostMallocDefault),
+                "hipHostMalloc", err);
+  if (r) return r;
+  std::memset(hctrl_, 0, sizeof(Ctrl));
+
+  bool ok = true;
+  auto D = [&](size_t count) -> double * {
+    double *p = (double *)dalloc(count * sizeof(double));
+    ok = ok && p;
+    return p;
+  };
+  auto I = [&](size_t count) -> int32_t * {
+    int32_t *p = (int32_t *)dalloc(count * sizeof(int32_t));
+    ok = ok && p;
+    return p;
+  };
+  ctrl_ = (Ctrl *)dalloc(sizeof(Ctrl));
+  ok = ok && ctrl_;
+  Qp_ = I(n + 1); Qi_ = I(nzq); Qraw_ = D(nzq); Qv_ = D(nzq);
+  Ap_ = I(m + 1); Ai_ = I(nza); Araw_ = D(nza); Av_ = D(nza);
+  ATp_ = I(n + 1); ATi_ = I(nza); ATraw_ = D(nza); ATv_ = D(nza);
+  atperm_ = I(nza);
+  craw_ = D(n); xlraw_ = D(n); xuraw_ = D(n); braw_ = D(m);
+  c_ = D(n); lo_ = D(n); hi_ = D(n); b_ = D(m);
+  v_.c = c_; v_.lo = lo_; v_.hi = hi_; v_.b = b_;
+  v_.sigma = D(m); v_.lam = D(m); v_.z = D(n); v_.qx = D(n);
+  v_.taub_x = D(n); v_.taub_s = D(mi); v_.taub_r = D(m); v_.etab = D(m);
+  v_.S2x = D(n); v_.S2s = D(mi); v_.S2r = D(m); v_.E2 = D(m);
+  for (int k = 0; k < 2; ++k) {
+    v_.X[k] = D(n); v_.QX[k] = D(n); v_.ATY[k] = D(n);
+    v_.S[k] = D(mi); v_.R[k] = D(m); v_.Y[k] = D(m); v_.BW[k] = D(m);
+  }
+  v_.xbar = D(n); v_.qxbar = D(n); v_.sbar = D(mi); v_.rbar = D(m); v_.ybar = D(m);
+  v_.xa = D(n); v_.sa = D(mi); v_.ra = D(m); v_.ya = D(m);
+  v_.axbar = D(m); v_.atybar = D(n);
+  v_.ax = D(m); v_.rrow = D(m); v_.rprev = D(m); v_.atl = D(n); v_.qxo = D(n);
+  v_.Dx = D(n); v_.Dc = D(m); v_.Ex = nullptr;
+  v_.Fx = D(n); v_.Fs = D(mi); v_.Fr = D(m); v_.tmp_n = D(n); v_.tmp_m = D(m);
+  Fx2_ = D(n); Fs2_ = D(mi); Fr2_ = D(m); E2buf_ = D(m);
+  v_.partial = D((size_t)kMaxParts * 32);
+  if (!ok) {
+    err = "device allocation failed";
+    return PDNQP_E_NOMEM;
+  }
+  auto H2D = [&](void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream_);
+  };
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chain(H2D(Qp_, qp_.Qp.data(), (n + 1) * 4));
+  chain(H2D(Qi_, qp_.Qi.data(), nzq * 4));
+  chain(H2D(Qraw_, qp_.Qx.data(), nzq * 8));
+  chain(H2D(Ap_, qp_.Ap.data(), (m + 1) * 4));
+  chain(H2D(Ai_, qp_.Ai.data(), nza * 4));
+  chain(H2D(Araw_, qp_.Ax.data(), nza * 8));
+  chain(H2D(ATp_, qp_.ATp.data(), (n + 1) * 4));
+  chain(H2D(ATi_, qp_.ATi.data(), nza * 4));
+  chain(H2D(ATraw_, qp_.ATx.data(), nza * 8));
+  chain(H2D(atperm_, qp_.ATperm.data(), nza * 4));
+  chain(H2D(craw_, qp_.c.data(), n * 8));
+  chain(H2D(xlraw_, qp_.xl.data(), n * 8));
+  chain(H2D(xuraw_, qp_.xu.data(), n * 8));
+  chain(H2D(braw_, qp_.b.data(), m * 8));
+  chain(hipStreamSynchronize(stream_));
+  if ((r = check(e, "upload", err))) return r;
+
+  const int GQ = pick_G(nzq, n), GA = pick_G(nza, m), GT = pick_G(nza, n);
+  Q_ = Csr{Qp_, Qi_, Qv_, n, GQ};
+  A_ = Csr{Ap_, Ai_, Av_, m, GA};
+  AT_ = Csr{ATp_, ATi_, ATv_, n, GT};
+  Qr_ = Csr{Qp_, Qi_, Qraw_, n, GQ};
+  Ar_ = Csr{Ap_, Ai_, Araw_, m, GA};
+  ATr_ = Csr{ATp_, ATi_, ATraw_, n, GT};
+  px_ = make_part(n, 1, 512);
+  ps_ = make_part(mi, 1, 256);
+  pr_ = make_part(m, 1, 256);
+  pq_ = make_part(n, GQ, 1024);
+  pa_ = make_part(m, GA, 1024);
+  pt_ = make_part(n, GT, 1024);
+  ip_ = InnerParams{};
+  ip_.n = n; ip_.m = m; ip_.me = qp_.me; ip_.mi = mi; ip_.dw = n + mi + m;
+  timers_.resize(TM_COUNT);
+  timers_[TM_XTRIAL].name = "xtrial";
+  timers_[TM_QA].name = "qa_spmv";
+  timers_[TM_AT].name = "at_spmv_accept";
+  const double me = qp_.me;
+  timers_[TM_XTRIAL].bytes = 12.0 * 8.0 * n;
+  timers_[TM_QA].bytes = 12.0 * nzq + 4.0 * (n + 1) + 16.0 * n + 12.0 * nza + 4.0 * (m + 1) +
+                         8.0 * n + 15.0 * 8.0 * me + 20.0 * 8.0 * mi;
+  timers_[TM_AT].bytes = 12.0 * nza + 4.0 * (n + 1) + 8.0 * m + 8.0 * n + 5.0 * 8.0 * n;
+  return PDNQP_OK;
+}
+
+void Solver::timed_launch(int which, const std::function<void()> &f) {
+  if (!st_.profile) {
+    f();
+    return;
+  }
+  KernelTimer &t = timers_[which];
+  if ((int)t.ev.size() < 2 * (t.used + 1)) {
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    t.ev.push_back(a);
+    t.ev.push_back(b);
+  }
+  hipEventRecord(t.ev[2 * t.used], stream_);
+  f();
+  hipEventRecord(t.ev[2 * t.used + 1], stream_);
+  t.used += 1;
+}
+
+void Solver::harvest_timers() {
+  if (!st_.profile) return;
+  for (auto &t : timers_) {
+    for (int k = 0; k < t.used; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]) == hipSuccess) {
+        t.total_ms += ms;
+        t.launches += 1;
+      }
+    }
+    t.used = 0;
+  }
+}
+
+int Solver::read_ctrl(std::string &err) {
+  int r = check(hipMemcpyAsync(hctrl_, ctrl_, sizeof(Ctrl), hipMemcpyDeviceToHost, stream_),
+                "ctrl readback", err);
+  if (r) return r;
+  r = check(hipStreamSynchronize(stream_), "hipStreamSynchronize", err);
+  if (r) return r;
+  harvest_timers();
+  return PDNQP_OK;
+}
+
+// Smallest eigenvalue estimate of the scaled Q by plain Lanczos (three-term
+// recurrence from the normalised all-ones vector, no reorthogonalisation).
+double Solver::lanczos(std::string &err, bool &ok) {
+  const int32_t n = qp_.n;
+  const int k = std::min<int>(st_.lanczos_iters, n);
+  // ||Q||_inf for the breakdown threshold
+  launch_row_abssum(stream_, Q_, v_.tmp_n, pq_);
+  launch_absmax(stream_, ctrl_, v_.tmp_n, n, 3, v_.partial);
+  ok = read_ctrl(err) == PDNQP_OK;
+  if (!ok) return 0.0;
+  const double qnorm = std::max(1.0, hctrl_->gen[3]);
+  double *vv = v_.qxo, *vp = v_.atl, *w = v_.tmp_n;
+  launch_fill(stream_, vv, 1.0 / std::sqrt((double)n), n);
+  launch_fill(stream_, vp, 0.0, n);
+  std::vector<double> al, be;
+  double beta_prev = 0.0;
+  for (int j = 0; j < k; ++j) {
+    launch_spmv(stream_, Q_, vv, w, 1.0, pq_);
+    launch_dot(stream_, ctrl_, vv, w, n, 0, v_.partial);
+    launch_lanczos_update(stream_, ctrl_, w, vv, vp, beta_prev, n, v_.partial);
+    ok = read_ctrl(err) == PDNQP_OK;
+    if (!ok) return 0.0;
+    const double alpha = hctrl_->gen[0];
+    const double beta = std::sqrt(hctrl_->gen[1]);
+    al.push_back(alpha);
+    if (j == k - 1 || beta <= 1e-14 * qnorm) break;
+    be.push_back(beta);
+    launch_copy(stream_, vp, vv, n);
+    launch_elem(stream_, EL_AXPBY, vv, w, nullptr, beta, n);
+    beta_prev = beta;
+  }
+  if (al.size() == 1) return al[0];
+  return tridiag_min_eig(al, be);
+}
+
+// Outer scaling (Section 3.1), objective scalar, scaled data.
+int Solver::setup(const double *x0c, const double *lam0_int, double &c_obj, double &gamma,
+                  double &lam_hat, std::string &err) {
+  const int32_t n = qp_.n, m = qp_.m, me = qp_.me;
+  hipError_t e = hipMemcpyAsync(v_.X[0], x0c, n * 8, hipMemcpyHostToDevice, stream_);
+  if (m) {
+    hipError_t e2 = hipMemcpyAsync(v_.lam, lam0_int, m * 8, hipMemcpyHostToDevice, stream_);
+    if (e == hipSuccess) e = e2;
+  }
+  int r = check(e, "upload x0/lambda0", err);
+  if (r) return r;
+  launch_fill(stream_, v_.Dc, 1.0, m);
+  launch_fill(stream_, v_.Dx, 1.0, n);
+  if (st_.outer_scaling != PDNQP_SCALE_NONE) {
+    const bool withq = st_.outer_scaling == PDNQP_SCALE_RUIZ_QA;
+    for (int sw = 0; sw < st_.ruiz_sweeps; ++sw) {
+      launch_row_absmax(stream_, Ar_, v_.Dc, v_.Dx, v_.tmp_m, pa_);
+      launch_fill(stream_, v_.tmp_n, 0.0, n);
+      launch_row_absmax(stream_, ATr_, v_.Dx, v_.Dc, v_.tmp_n, pt_);
+      if (withq) launch_row_absmax(stream_, Qr_, v_.Dx, v_.Dx, v_.qxo, pq_);
+      launch_ruiz_update(stream_, v_.Dc, v_.tmp_m, m, v_.Dx, v_.tmp_n, withq ? v_.qxo : nullptr,
+                         n);
+    }
+  }
+  // c_obj = 1 / max(1, ||Dx (Q x0 + c)||_inf)
+  launch_spmv(stream_, Qr_, v_.X[0], v_.tmp_n, 1.0, pq_);
+  launch_elem(stream_, EL_GRAD, v_.tmp_n, v_.Dx, craw_, 0.0, n);
+  launch_absmax(stream_, ctrl_, v_.tmp_n, n, 0, v_.partial);
+  if ((r = read_ctrl(err))) return r;
+  c_obj = 1.0 / std::max(1.0, hctrl_->gen[0]);
+  // scaled values: Q <- c_obj Dx Q Dx, A <- Dc A Dx, A' gathered from A
+  hipMemcpyAsync(Qv_, Qraw_, Q_.rows ? qp_.Qi.size() * 8 : 0, hipMemcpyDeviceToDevice, stream_);
+  hipMemcpyAsync(Av_, Araw_, qp_.Ai.size() * 8, hipMemcpyDeviceToDevice, stream_);
+  launch_scale_csr(stream_, Qp_, Qi_, Qv_, n, v_.Dx, v_.Dx, c_obj, pq_);
+  launch_scale_csr(stream_, Ap_, Ai_, Av_, m, v_.Dc, v_.Dx, 1.0, pa_);
+  launch_gather(stream_, ATv_, Av_, atperm_, (int64_t)qp_.Ai.size());
+  launch_elem(stream_, EL_MULS, c_, v_.Dx, craw_, c_obj, n);
+  launch_elem(stream_, EL_MUL, b_, v_.Dc, braw_, 0.0, m);
+  launch_elem(stream_, EL_DIV, lo_, xlraw_, v_.Dx, 0.0, n);
+  launch_elem(stream_, EL_DIV, hi_, xuraw_, v_.Dx, 0.0, n);
+  launch_elem(stream_, EL_DIVINTO, v_.X[0], v_.Dx, nullptr, 0.0, n);
+  launch_elem(stream_, EL_SCALE_DIV, v_.lam, v_.lam, v_.Dc, c_obj, m);
+  // proximal step (R-choice)
+  if (st_.gamma_override > 0) {
+    gamma = st_.gamma_override;
+    lam_hat = std::numeric_limits<double>::quiet_NaN();
+  } else {
+    bool ok = true;
+    lam_hat = lanczos(err, ok);
+    if (!ok) return PDNQP_E_DEVICE;
+    launch_row_abssum(stream_, Q_, v_.tmp_n, pq_);
+    launch_absmax(stream_, ctrl_, v_.tmp_n, n, 3, v_.partial);
+    if ((r = read_ctrl(err))) return r;
+    const double qn = hctrl_->gen[3];
+    gamma = 1.0 / (std::max(0.0, -lam_hat) + st_.delta_gamma * std::max(1.0, qn));
+  }
+  // initial penalty (QPALM-style) and norms of the scaled data
+  launch_spmv(stream_, Q_, v_.X[0], v_.tmp_n, 1.0, pq_);
+  launch_dot(stream_, ctrl_, v_.X[0], v_.tmp_n, n, 0, v_.partial);
+  launch_dot(stream_, ctrl_, c_, v_.X[0], n, 1, v_.partial);
+  if (m) {
+    launch_spmv(stream_, A_, v_.X[0], v_.ax, 1.0, pa_);
+    launch_viol(stream_, ip_, v_, v_.tmp_m);
+    launch_dot(stream_, ctrl_, v_.tmp_m, v_.tmp_m, m, 2, v_.partial);
+    launch_absmax(stream_, ctrl_, b_, me, 4, v_.partial);
+    launch_absmax(stream_, ctrl_, b_ + me, m - me, 5, v_.partial);
+  }
+  launch_absmax(stream_, ctrl_, c_, n, 6, v_.partial);
+  if ((r = read_ctrl(err))) return r;
+  const double f = 0.5 * hctrl_->gen[0] + hctrl_->gen[1];
+  const double vv = m ? hctrl_->gen[2] : 0.0;
+  bE_norm_ = (m && me) ? hctrl_->gen[4] : 0.0;
+  bI_norm_ = (m && m > me) ? hctrl_->gen[5] : 0.0;
+  c_norm_ = hctrl_->gen[6];
+  double s0 = st_.sigma_init * std::max(1.0, std::fabs(f)) / std::max(1.0, 0.5 * vv);
+  s0 = std::min(std::max(s0, st_.sigma0_min), st_.sigma0_max);
+  launch_fill(stream_, v_.sigma, s0, m);
+  launch_copy(stream_, v_.z, v_.X[0], n);
+  launch_elem(stream_, EL_NEG, v_.Y[0], v_.lam, nullptr, 0.0, m);
+  return check(hipGetLastError(), "setup kernels", err);
+}
+
+// Warm start, inner scaling and steps, starting products and anchor metric.
+void Solver::form_inner(double gamma) {
+  const int cur = hctrl_->cur;
+  launch_spmv(stream_, A_, v_.X[cur], v_.ax, 1.0, pa_);
+  launch_warm(stream_, ip_, v_, cur, gamma);
+  launch_fill(stream_, v_.tmp_m, 1.0, qp_.m);
+  launch_fill(stream_, v_.Fx, 1.0, qp_.n);
+  launch_fill(stream_, v_.Fs, 1.0, qp_.mi);
+  launch_fill(stream_, v_.Fr, 1.0, qp_.m);
+  if (qp_.m > 0) {
+    for (int sw = 0; sw < st_.ruiz_sweeps; ++sw) {
+      launch_inner_ruiz_sweep(stream_, ip_, v_, A_, AT_, pa_, pt_, Fx2_, Fs2_, Fr2_, E2buf_);
+      std::swap(v_.Fx, Fx2_);
+      std::swap(v_.Fs, Fs2_);
+      std::swap(v_.Fr, Fr2_);
+      std::swap(v_.tmp_m, E2buf_);
+    }
+  }
+  launch_steps(stream_, ip_, v_, Q_, A_, AT_, 1.0 / gamma, st_.step_boost);
+  launch_inner_init(stream_, ctrl_, ip_, v_, Q_, AT_, pq_, pr_, gamma);
+  InnerParams pi = ip_;
+  pi.mode_init = 1;
+  launch_check(stream_, ctrl_, pi, v_, px_, ps_, pr_);
+}
+
+int Solver::run_inner(double deadline, std::string &err) {
+  for (;;) {
+    const int t = hctrl_->t, tc = hctrl_->t_call;
+    int slots = st_.check_every - (t % st_.check_every);
+    slots = std::min(slots, st_.max_inner - tc);
+    slots = std::max(slots, 1);
+    for (int s = 0; s < slots; ++s) {
+      timed_launch(TM_XTRIAL, [&] { launch_xtrial(stream_, ctrl_, ip_, v_, px_); });
+      timed_launch(TM_QA, [&] { launch_qa(stream_, ctrl_, ip_, v_, Q_, A_, pq_, pa_); });
+      timed_launch(TM_AT, [&] { launch_at(stream_, ctrl_, ip_, v_, AT_, pt_); });
+      if (trace_iters_cap_ > 0) launch_trace(stream_, ctrl_, ip_, v_, px_, pr_);
+    }
+    launch_flush(stream_, ctrl_, ip_, v_, px_, pr_);
+    launch_check_spmv(stream_, ctrl_, ip_, v_, A_, AT_, pa_, pt_);
+    launch_check(stream_, ctrl_, ip_, v_, px_, ps_, pr_);
+    launch_apply(stream_, ctrl_, ip_, v_, px_, pr_);
+    int r = check(hipGetLastError(), "inner launches", err);
+    if (r) return -1000 + r;
+    if ((r = read_ctrl(err))) return -1000 + r;
+    const int state = hctrl_->state;
+    if (state == ST_RUNNING) {
+      if (now_s() > deadline) return ST_RUNNING;
+      continue;
+    }
+    return state;
+  }
+}
+
+int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double *lam0,
+                  double *x_out, double *lam_out, pdnqp_info *info, std::string &err) {
+  const double t_start = now_s();
+  const double deadline =
+      std::isfinite(st_.time_limit_s) ? t_start + st_.time_limit_s : std::numeric_limits<double>::infinity();
+  const int32_t n = qp_.n, m = qp_.m, me = qp_.me, mi = qp_.mi;
+  const int dw = n + mi + m;
+  int r;
+  // trace buffers
+  traced_ = false;
+  trace_iters_cap_ = std::max(0, st_.trace_iters);
+  trace_trials_cap_ = std::max(0, st_.trace_trials);
+  if (trace_iters_cap_ > 0 && !tw_) {
+    tw_ = (double *)dalloc((size_t)trace_iters_cap_ * dw * 8);
+    ty_ = (double *)dalloc((size_t)trace_iters_cap_ * std::max(m, 1) * 8);
+    if (!tw_ || !ty_) {
+      err = "trace allocation failed";
+      return PDNQP_E_NOMEM;
+    }
+  }
+  if (trace_trials_cap_ > 0 && !ttr_) {
+    ttr_ = (double *)dalloc((size_t)trace_trials_cap_ * 3 * 8);
+    tck_ = (int32_t *)dalloc((size_t)trace_trials_cap_ * 4 * 4);
+    if (!ttr_ || !tck_) {
+      err = "trace allocation failed";
+      return PDNQP_E_NOMEM;
+    }
+  }
+  v_.trace_w = tw_;
+  v_.trace_y = ty_;
+  v_.trace_tr = ttr_;
+  v_.trace_ck = tck_;
+  ip_.trace_iters_cap = trace_iters_cap_;
+  ip_.trace_trials_cap = trace_trials_cap_;
+  for (auto &t : timers_) {
+    t.launches = 0;
+    t.total_ms = 0.0;
+    t.used = 0;
+  }
+  // host-side start: x0 clipped into the box, lambda0 in internal rows
+  std::vector<double> x0c(n, 0.0), lam0i(m, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double x = x0 ? x0[i] : 0.0;
+    x0c[i] = x < qp_.xl[i] ? qp_.xl[i] : (x > qp_.xu[i] ? qp_.xu[i] : x);
+  }
+  if (lam0) {
+    for (int j = 0; j < m; ++j) {
+      double l = qp_.sign_of[j] * lam0[qp_.row_of[j]];
+      if (j >= me) l = std::min(l, 0.0);
+      lam0i[j] = l;
+    }
+  }
+  // control block
+  Ctrl hc;
+  std::memset(&hc, 0, sizeof(hc));
+  hc.state = ST_RUNNING;
+  hc.cur = 0;
+  hc.omega = st_.omega0;
+  hc.step_scale = 1.0;
+  hc.kkt_prev = std::numeric_limits<double>::infinity();
+  *hctrl_ = hc;
+  if ((r = check(hipMemcpyAsync(ctrl_, hctrl_, sizeof(Ctrl), hipMemcpyHostToDevice, stream_),
+                 "ctrl upload", err)))
+    return r;
+  double c_obj = 1.0, gamma = 0.0, lam_hat = 0.0;
+  if ((r = setup(x0c.data(), lam0i.data(), c_obj, gamma, lam_hat, err))) return r;
+  if ((r = read_ctrl(err))) return r;
+  const double t_setup = now_s() - t_start;
+  gamma_ = gamma;
+  ip_.gamma_inv = 1.0 / gamma;
+  ip_.h_norm = bE_norm_;
+  ip_.check_every = st_.check_every;
+  ip_.max_inner = st_.max_inner;
+  ip_.max_rejects = st_.max_rejects;
+  ip_.shrink_safety = st_.shrink_safety;
+  ip_.shrink_min = st_.shrink_min;
+  ip_.shrink_max = st_.shrink_max;
+  ip_.restart_suff = st_.restart_suff;
+  ip_.restart_nec = st_.restart_nec;
+  ip_.restart_art = st_.restart_art;
+  ip_.mode_init = 0;
+
+  double delta_a = 1.0, delta_r = 1.0, eps_ak = 1.0, eps_rk = 1.0;
+  bool have_prev = false, need_form = true;
+  int status = PDNQP_MAX_ITER;
+  int64_t k = 0;
+  double rp = NAN, rd = NAN, sp = NAN, sd = NAN;
+  while (k < st_.max_outer) {
+    ip_.delta_a = delta_a;
+    ip_.delta_r = delta_r;
+    if (need_form) {
+      form_inner(gamma);
+      if ((r = read_ctrl(err))) return r;
+    }
+    const int ist = run_inner(deadline, err);
+    if (ist <= -1000) return ist + 1000;
+    k += 1;
+    if (ist == ST_NUMERR) {
+      status = PDNQP_NUMERICAL_ERROR;
+      break;
+    }
+    if (ist == ST_RUNNING) {  // deadline inside the inner solve
+      status = PDNQP_TIME_LIMIT;
+      break;
+    }
+    if (ist == ST_ITER_LIMIT) {
+      // keep the outer variables and continue the inner solve
+      need_form = false;
+      hctrl_->state = ST_RUNNING;
+      hctrl_->t_call = 0;
+      if ((r = check(hipMemcpyAsync(ctrl_, hctrl_, offsetof(Ctrl, alpha_pend),
+                                    hipMemcpyHostToDevice, stream_),
+                     "ctrl update", err)))
+        return r;
+      if (now_s() > deadline) {
+        status = PDNQP_TIME_LIMIT;
+        break;
+      }
+      continue;
+    }
+    // multiplier update and outer residuals
+    if (m) launch_outer_rows(stream_, ctrl_, ip_, v_, A_, pa_);
+    launch_outer_cols(stream_, ctrl_, ip_, v_, Q_, AT_, pq_);
+    if ((r = read_ctrl(err))) return r;
+    const double *ov = hctrl_->outv;
+    rp = m ? ov[0] : 0.0;
+    sp = std::max({1.0, m ? ov[1] : 0.0, bE_norm_, m ? ov[2] : 0.0, bI_norm_});
+    rd = ov[4];
+    sd = std::max({1.0, ov[5], c_norm_, ov[6]});
+    const double dxz = ov[7];
+    const double rn = m ? ov[3] : 0.0;
+    if (rp <= eps_abs + eps_rel * sp && rd <= eps_abs + eps_rel * sd) {
+      status = PDNQP_SOLVED;
+      break;
+    }
+    // row penalties (penalty-trigger-eq)
+    launch_penalty(stream_, ip_, v_, pr_, have_prev ? 1 : 0, rn, st_.theta_sigma,
+                   st_.sigma_growth, st_.sigma_max, st_.penalty_gate, eps_abs + eps_rel * sp);
+    have_prev = true;
+    // inner tolerances (inner-tolerance-factor)
+    const double ratio = (rd == 0.0) ? 1.0 : std::min(1.0, dxz / gamma / rd);
+    const double rho = st_.rho_in_max - (st_.rho_in_max - st_.rho_in_min) * ratio;
+    delta_a = std::max(eps_abs, rho * delta_a);
+    delta_r = std::max(eps_rel, rho * delta_r);
+    // proximal centre (center-update)
+    if (rp <= eps_ak + eps_rk * sp) {
+      launch_copy(stream_, v_.z, v_.X[hctrl_->cur], n);
+      eps_ak *= st_.rho_z;
+      eps_rk *= st_.rho_z;
+    }
+    need_form = true;
+    if (now_s() > deadline) {
+      status = PDNQP_TIME_LIMIT;
+      break;
+    }
+  }
+  // unscale: x = Dx x_bar, lambda = Dc lambda_bar / c_obj, then caller's rows
+  const int cur = hctrl_->cur;
+  launch_elem(stream_, EL_MUL, v_.tmp_n, v_.Dx, v_.X[cur], 0.0, n);
+  launch_elem(stream_, EL_MUL, v_.tmp_m, v_.Dc, v_.lam, 0.0, m);
+  std::vector<double> xs(n), ls(m);
+  hipMemcpyAsync(xs.data(), v_.tmp_n, n * 8, hipMemcpyDeviceToHost, stream_);
+  if (m) hipMemcpyAsync(ls.data(), v_.tmp_m, m * 8, hipMemcpyDeviceToHost, stream_);
+  if (trace_iters_cap_ > 0 || trace_trials_cap_ > 0) {
+    got_iters_ = hctrl_->trace_iters_n;
+    got_trials_ = hctrl_->trace_trials_n;
+    got_checks_ = hctrl_->trace_checks_n;
+    h_tw_.assign((size_t)got_iters_ * dw, 0.0);
+    h_ty_.assign((size_t)got_iters_ * m, 0.0);
+    h_ttr_.assign((size_t)got_trials_ * 3, 0.0);
+    h_tck_.assign((size_t)got_checks_ * 4, 0);
+    if (got_iters_) {
+      hipMemcpyAsync(h_tw_.data(), tw_, h_tw_.size() * 8, hipMemcpyDeviceToHost, stream_);
+      if (m) hipMemcpyAsync(h_ty_.data(), ty_, h_ty_.size() * 8, hipMemcpyDeviceToHost, stream_);
+    }
+    if (got_trials_)
+      hipMemcpyAsync(h_ttr_.data(), ttr_, h_ttr_.size() * 8, hipMemcpyDeviceToHost, stream_);
+    if (got_checks_)
+      hipMemcpyAsync(h_tck_.data(), tck_, h_tck_.size() * 4, hipMemcpyDeviceToHost, stream_);
+    traced_ = true;
+  }
+  if ((r = check(hipStreamSynchronize(stream_), "final copy", err))) return r;
+  if ((r = check(hipGetLastError(), "final kernels", err))) return r;
+  for (int j = 0; j < m; ++j) ls[j] = ls[j] / c_obj;
+  std::vector<double> lam_orig(qp_.m_orig, 0.0);
+  for (int j = 0; j < m; ++j) lam_orig[qp_.row_of[j]] += qp_.sign_of[j] * ls[j];
+  if (x_out) std::memcpy(x_out, xs.data(), n * 8);
+  if (lam_out && qp_.m_orig) std::memcpy(lam_out, lam_orig.data(), qp_.m_orig * 8);
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->outer_iters = k;
+    info->inner_trials = hctrl_->trials;
+    info->inner_accepted = hctrl_->accepted;
+    info->inner_rejected = hctrl_->rejected;
+    info->restarts = hctrl_->restarts;
+    info->checks = hctrl_->checks;
+    info->r_p_scaled = rp;
+    info->r_d_scaled = rd;
+    info->s_p_scaled = sp;
+    info->s_d_scaled = sd;
+    info->gamma = gamma;
+    info->lambda_hat = lam_hat;
+    info->omega = hctrl_->omega;
+    info->setup_s = t_setup;
+    external_check(xs, lam_orig, info);
+    info->solve_s = now_s() - t_start;
+  }
+  return PDNQP_OK;
+}
+
+// KKT test on the caller's (unscaled) problem: primal residual with bound
+// violation, projected stationarity, scales as in (outer-scales).
+void Solver::external_check(const std::vector<double> &x, const std::vector<double> &lam,
+                            pdnqp_info *info) const {
+  const int32_t n = qp_.n, mo = qp_.m_orig;
+  std::vector<double> ax(mo, 0.0), qx(n, 0.0), atl(n, 0.0);
+  for (int j = 0; j < mo; ++j) {
+    double s = 0.0;
+    for (int k = qp_.oAp[j]; k < qp_.oAp[j + 1]; ++k) s += qp_.oAx[k] * x[qp_.oAi[k]];
+    ax[j] = s;
+    for (int k = qp_.oAp[j]; k < qp_.oAp[j + 1]; ++k) atl[qp_.oAi[k]] += qp_.oAx[k] * lam[j];
+  }
+  double obj = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int k = qp_.Qp[i]; k < qp_.Qp[i + 1]; ++k) s += qp_.Qx[k] * x[qp_.Qi[k]];
+    qx[i] = s;
+    obj += 0.5 * x[i] * s + qp_.c[i] * x[i];
+  }
+  double rp = 0.0, rd = 0.0, sp = 1.0, sd = 1.0;
+  for (int j = 0; j < mo; ++j) {
+    const double v = std::max({qp_.orl[j] - ax[j], ax[j] - qp_.oru[j], 0.0});
+    rp = std::max(rp, v);
+    sp = std::max(sp, std::fabs(ax[j]));
+    if (std::isfinite(qp_.orl[j])) sp = std::max(sp, std::fabs(qp_.orl[j]));
+    if (std::isfinite(qp_.oru[j])) sp = std::max(sp, std::fabs(qp_.oru[j]));
+  }
+  for (int i = 0; i < n; ++i) {
+    rp = std::max({rp, qp_.xl[i] - x[i], x[i] - qp_.xu[i]});
+    double t = x[i] - qx[i] - qp_.c[i] - atl[i];
+    t = t < qp_.xl[i] ? qp_.xl[i] : (t > qp_.xu[i] ? qp_.xu[i] : t);
+    rd = std::max(rd, std::fabs(x[i] - t));
+    sd = std::max({sd, std::fabs(qx[i]), std::fabs(qp_.c[i]), std::fabs(atl[i])});
+  }
+  info->r_p = rp;
+  info->r_d = rd;
+  info->s_p = sp;
+  info->s_d = sd;
+  info->objective = obj;
+}
+
+int Solver::trace(int32_t *iters, double *w, double *y, int32_t *trials, double *tr,
+                  int32_t *checks, int32_t *ck) const {
+  if (!traced_) return PDNQP_E_STATE;
+  if (iters) *iters = got_iters_;
+  if (trials) *trials = got_trials_;
+  if (checks) *checks = got_checks_;
+  if (w && !h_tw_.empty()) std::memcpy(w, h_tw_.data(), h_tw_.size() * 8);
+  if (y && !h_ty_.empty()) std::memcpy(y, h_ty_.data(), h_ty_.size() * 8);
+  if (tr && !h_ttr_.empty()) std::memcpy(tr, h_ttr_.data(), h_ttr_.size() * 8);
+  if (ck && !h_tck_.empty()) std::memcpy(ck, h_tck_.data(), h_tck_.size() * 4);
+  return PDNQP_OK;
+}
+
+int Solver::kernel_stats(pdnqp_kernel_stat *out, int32_t cap, int32_t *count) const {
+  const int nt = (int)timers_.size();
+  if (count) *count = nt;
+  for (int k = 0; k < nt && k < cap && out; ++k) {
+    std::memset(&out[k], 0, sizeof(out[k]));
+    std::strncpy(out[k].name, timers_[k].name.c_str(), sizeof(out[k].name) - 1);
+    out[k].launches = timers_[k].launches;
+    out[k].total_ms = timers_[k].total_ms;
+    out[k].avg_us = timers_[k].launches ? 1000.0 * timers_[k].total_ms / timers_[k].launches : 0.0;
+    out[k].bytes_per_launch = timers_[k].bytes;
+  }
+  return PDNQP_OK;
+}
+
+}  // namespace pdnqp

@@ -1,0 +1,322 @@
+"""Python binding of ``libpdnqp.so`` (the gfx950 PDNQP library).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  The library must have been built (``build.py``); loading fails
+loudly otherwise.  PyTorch, when asked for (``use_torch=True``), provides the
+HIP stream and the device memory (its caching allocator) -- nothing else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdnqp.so")
+
+OK = 0
+E_INVALID, E_NOMEM, E_DEVICE, E_STATE = -1, -2, -3, -4
+SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR = 1, 2, 3, 4
+STATUS_NAMES = {SOLVED: "solved", MAX_ITER: "max_iter", TIME_LIMIT: "time_limit",
+                NUMERICAL_ERROR: "numerical_error"}
+SCALE_RUIZ_A, SCALE_NONE, SCALE_RUIZ_QA = 0, 1, 2
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Settings(ctypes.Structure):
+    _fields_ = [
+        ("max_outer", ctypes.c_int64),
+        ("max_inner", ctypes.c_int32),
+        ("ruiz_sweeps", ctypes.c_int32),
+        ("time_limit_s", ctypes.c_double),
+        ("sigma_init", ctypes.c_double),
+        ("theta_sigma", ctypes.c_double),
+        ("delta_gamma", ctypes.c_double),
+        ("rho_in_min", ctypes.c_double),
+        ("rho_in_max", ctypes.c_double),
+        ("rho_z", ctypes.c_double),
+        ("check_every", ctypes.c_int32),
+        ("max_rejects", ctypes.c_int32),
+        ("restart_suff", ctypes.c_double),
+        ("restart_nec", ctypes.c_double),
+        ("restart_art", ctypes.c_double),
+        ("shrink_safety", ctypes.c_double),
+        ("shrink_min", ctypes.c_double),
+        ("shrink_max", ctypes.c_double),
+        ("omega0", ctypes.c_double),
+        ("sigma_growth", ctypes.c_double),
+        ("sigma_max", ctypes.c_double),
+        ("sigma0_min", ctypes.c_double),
+        ("sigma0_max", ctypes.c_double),
+        ("penalty_gate", ctypes.c_int32),
+        ("lanczos_iters", ctypes.c_int32),
+        ("gamma_override", ctypes.c_double),
+        ("step_boost", ctypes.c_double),
+        ("outer_scaling", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("trace_iters", ctypes.c_int32),
+        ("trace_trials", ctypes.c_int32),
+        ("hip_stream", ctypes.c_void_p),
+        ("dev_alloc", _ALLOC_FN),
+        ("dev_free", _FREE_FN),
+        ("alloc_user", ctypes.c_void_p),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("outer_iters", ctypes.c_int64),
+        ("inner_trials", ctypes.c_int64),
+        ("inner_accepted", ctypes.c_int64),
+        ("inner_rejected", ctypes.c_int64),
+        ("restarts", ctypes.c_int64),
+        ("checks", ctypes.c_int64),
+        ("r_p", ctypes.c_double),
+        ("r_d", ctypes.c_double),
+        ("s_p", ctypes.c_double),
+        ("s_d", ctypes.c_double),
+        ("r_p_scaled", ctypes.c_double),
+        ("r_d_scaled", ctypes.c_double),
+        ("s_p_scaled", ctypes.c_double),
+        ("s_d_scaled", ctypes.c_double),
+        ("objective", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("lambda_hat", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("setup_s", ctypes.c_double),
+        ("solve_s", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d["status_name"] = STATUS_NAMES.get(self.status, str(self.status))
+        return d
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("avg_us", ctypes.c_double),
+        ("bytes_per_launch", ctypes.c_double),
+    ]
+
+
+EXPORTED = ["pdnqp_default_settings", "pdnqp_settings_size", "pdnqp_info_size", "pdnqp_create",
+            "pdnqp_solve", "pdnqp_solve_batch", "pdnqp_destroy", "pdnqp_last_error",
+            "pdnqp_dims", "pdnqp_get_trace", "pdnqp_kernel_stats"]
+
+_lib = None
+
+
+class PdnqpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pdnqp error {code}: {msg}")
+        self.code = code
+
+
+def load(path=None):
+    """Loads the library (once).  Raises if it is missing or mismatched."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} not found: build it first (python -m paper_2609_19557_amd.build)")
+    lib = ctypes.CDLL(p)
+    i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    P = ctypes.POINTER
+    lib.pdnqp_default_settings.argtypes = [P(Settings)]
+    lib.pdnqp_default_settings.restype = None
+    lib.pdnqp_settings_size.restype = ctypes.c_size_t
+    lib.pdnqp_info_size.restype = ctypes.c_size_t
+    lib.pdnqp_create.argtypes = [P(vp), i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                 P(Settings)]
+    lib.pdnqp_create.restype = ctypes.c_int
+    lib.pdnqp_solve.argtypes = [vp, dbl, dbl, vp, vp, vp, vp, P(Info)]
+    lib.pdnqp_solve.restype = ctypes.c_int
+    lib.pdnqp_solve_batch.argtypes = [i32, P(vp), dbl, dbl, P(vp), P(vp), P(Info)]
+    lib.pdnqp_solve_batch.restype = ctypes.c_int
+    lib.pdnqp_destroy.argtypes = [vp]
+    lib.pdnqp_destroy.restype = None
+    lib.pdnqp_last_error.restype = ctypes.c_char_p
+    lib.pdnqp_dims.argtypes = [vp, P(i32), P(i32), P(i32)]
+    lib.pdnqp_dims.restype = ctypes.c_int
+    lib.pdnqp_get_trace.argtypes = [vp, P(i32), vp, vp, P(i32), vp, P(i32), vp]
+    lib.pdnqp_get_trace.restype = ctypes.c_int
+    lib.pdnqp_kernel_stats.argtypes = [vp, P(KernelStat), i32, P(i32)]
+    lib.pdnqp_kernel_stats.restype = ctypes.c_int
+    if lib.pdnqp_settings_size() != ctypes.sizeof(Settings):
+        raise ImportError("pdnqp_settings layout mismatch between library and binding")
+    if lib.pdnqp_info_size() != ctypes.sizeof(Info):
+        raise ImportError("pdnqp_info layout mismatch between library and binding")
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _err(lib, code):
+    return PdnqpError(code, lib.pdnqp_last_error().decode())
+
+
+def default_settings(**overrides):
+    lib = load()
+    s = Settings()
+    lib.pdnqp_default_settings(ctypes.byref(s))
+    for k, v in overrides.items():
+        if not hasattr(s, k):
+            raise KeyError(k)
+        setattr(s, k, v)
+    return s
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
+
+
+def _csr_parts(M, rows, cols):
+    import scipy.sparse as sp
+    M = sp.csr_matrix(M)
+    if M.shape != (rows, cols):
+        raise ValueError(f"matrix shape {M.shape} != {(rows, cols)}")
+    M.sort_indices()
+    return (np.ascontiguousarray(M.indptr, dtype=np.int32),
+            np.ascontiguousarray(M.indices, dtype=np.int32),
+            np.ascontiguousarray(M.data, dtype=np.float64))
+
+
+class _TorchPlumbing:
+    """Stream and caching-allocator callbacks from PyTorch."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.current_stream()
+        dev = torch.cuda.current_device()
+
+        def alloc(nbytes, user):
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self.stream)
+
+        def free(ptr, user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc_cb = _ALLOC_FN(alloc)
+        self.free_cb = _FREE_FN(free)
+
+
+class Solver:
+    """One QP on the GPU: ``min 1/2 x'Qx + c'x, rl <= Ax <= ru, xl <= x <= xu``."""
+
+    def __init__(self, Q, A, c, xl, xu, rl, ru, settings=None, use_torch=False, **overrides):
+        self.lib = load()
+        n = int(np.asarray(c).shape[0])
+        m = int(A.shape[0])
+        self.n, self.m = n, m
+        st = settings if settings is not None else default_settings()
+        for k, v in overrides.items():
+            setattr(st, k, v)
+        self._torch = None
+        if use_torch:
+            self._torch = _TorchPlumbing()
+            st.hip_stream = ctypes.c_void_p(self._torch.stream.cuda_stream)
+            st.dev_alloc = self._torch.alloc_cb
+            st.dev_free = self._torch.free_cb
+        self.settings = st
+        Qp, Qi, Qx = _csr_parts(Q, n, n)
+        Ap, Ai, Ax = _csr_parts(A, m, n)
+        self._keep = [np.ascontiguousarray(v, dtype=np.float64) for v in (c, xl, xu, rl, ru)]
+        c_, xl_, xu_, rl_, ru_ = self._keep
+        h = ctypes.c_void_p()
+        code = self.lib.pdnqp_create(ctypes.byref(h), n, m, _ptr(Qp), _ptr(Qi), _ptr(Qx),
+                                     Ap.ctypes.data_as(ctypes.c_void_p), _ptr(Ai), _ptr(Ax),
+                                     _ptr(c_), _ptr(xl_), _ptr(xu_), _ptr(rl_), _ptr(ru_),
+                                     ctypes.byref(st))
+        if code != OK:
+            raise _err(self.lib, code)
+        self.h = h
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        return cls(prob["Q"], prob["A"], prob["c"], prob["xl"], prob["xu"], prob["rl"],
+                   prob["ru"], **kw)
+
+    def solve(self, eps_abs=1e-4, eps_rel=1e-4, x0=None, lam0=None):
+        x = np.zeros(self.n)
+        lam = np.zeros(max(self.m, 1))
+        info = Info()
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        l0a = None if lam0 is None else np.ascontiguousarray(lam0, dtype=np.float64)
+        code = self.lib.pdnqp_solve(self.h, eps_abs, eps_rel, _ptr(x0a), _ptr(l0a),
+                                    x.ctypes.data_as(ctypes.c_void_p),
+                                    lam.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info))
+        if code != OK:
+            raise _err(self.lib, code)
+        return x, lam[:self.m], info.as_dict()
+
+    def dims(self):
+        me, mi, dw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        code = self.lib.pdnqp_dims(self.h, ctypes.byref(me), ctypes.byref(mi), ctypes.byref(dw))
+        if code != OK:
+            raise _err(self.lib, code)
+        return me.value, mi.value, dw.value
+
+    def trace(self):
+        it, ntr, nck = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        code = self.lib.pdnqp_get_trace(self.h, ctypes.byref(it), None, None, ctypes.byref(ntr),
+                                        None, ctypes.byref(nck), None)
+        if code != OK:
+            raise _err(self.lib, code)
+        me, mi, dw = self.dims()
+        mint = me + mi
+        w = np.zeros((it.value, dw))
+        y = np.zeros((it.value, max(mint, 1)))
+        tr = np.zeros((ntr.value, 3))
+        ck = np.zeros((nck.value, 4), dtype=np.int32)
+        code = self.lib.pdnqp_get_trace(self.h, ctypes.byref(it), _ptr(w), _ptr(y),
+                                        ctypes.byref(ntr), _ptr(tr), ctypes.byref(nck), _ptr(ck))
+        if code != OK:
+            raise _err(self.lib, code)
+        return dict(w=w, y=y[:, :mint], trials=tr, checks=ck)
+
+    def kernel_stats(self):
+        cnt = ctypes.c_int32()
+        self.lib.pdnqp_kernel_stats(self.h, None, 0, ctypes.byref(cnt))
+        arr = (KernelStat * max(cnt.value, 1))()
+        self.lib.pdnqp_kernel_stats(self.h, arr, cnt.value, ctypes.byref(cnt))
+        return [dict(name=a.name.decode(), launches=a.launches, total_ms=a.total_ms,
+                     avg_us=a.avg_us, bytes_per_launch=a.bytes_per_launch)
+                for a in arr[:cnt.value]]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pdnqp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(solvers, eps_abs=1e-4, eps_rel=1e-4):
+    """``pdnqp_solve_batch`` over a list of ``Solver``s."""
+    lib = load()
+    k = len(solvers)
+    xs = [np.zeros(s.n) for s in solvers]
+    ls = [np.zeros(max(s.m, 1)) for s in solvers]
+    hs = (ctypes.c_void_p * k)(*[s.h.value for s in solvers])
+    xp = (ctypes.c_void_p * k)(*[x.ctypes.data for x in xs])
+    lp = (ctypes.c_void_p * k)(*[l.ctypes.data for l in ls])
+    infos = (Info * k)()
+    code = lib.pdnqp_solve_batch(k, hs, eps_abs, eps_rel, xp, lp, infos)
+    if code != OK:
+        raise _err(lib, code)
+    return [(xs[i], ls[i][:solvers[i].m], infos[i].as_dict()) for i in range(k)]
