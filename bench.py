@@ -98,7 +98,7 @@ def main():
     sw.close()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
-    s = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=1)
+    s = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x, lam, info = s.solve(1e-4, 1e-4)

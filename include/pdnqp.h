@@ -94,9 +94,12 @@ typedef struct pdnqp_settings {
   double gamma_override;   /* > 0: use this proximal step instead of the Lanczos rule; 0 (default) */
   double step_boost;       /* multiplies the diagonal steps at every rebuild; 1 (testing knob) */
   int32_t outer_scaling;   /* PDNQP_SCALE_*, default PDNQP_SCALE_RUIZ_A */
-  int32_t profile;         /* 1: time the per-trial kernels with HIP events (pdnqp_kernel_stats) */
+  int32_t profile;         /* P > 0: time the per-trial kernels of one trial slot in every P with
+                              HIP events (pdnqp_kernel_stats); 0: off */
   int32_t trace_iters;     /* record unscaled inner (w, y) after each of the first N accepted trials */
   int32_t trace_trials;    /* record (L, R, accepted) of the first N trials and the first N checks */
+  int32_t verbose;         /* 1: one line per outer iteration on stderr */
+  int32_t center_floor;    /* [reading] centre-update tolerances never fall below eps_abs, eps_rel; 1 */
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */

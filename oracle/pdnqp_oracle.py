@@ -93,6 +93,9 @@ class Settings:
     # [reading] a row whose residual already meets the outer tolerance
     # (|r_i| <= eps_abs + eps_rel * s_p) is not penalised further
     penalty_gate: bool = True
+    # [reading] the centre-update tolerances are floored at the outer
+    # tolerances eps_abs, eps_rel (like the inner tolerances)
+    center_floor: bool = True
     # [reading] Lanczos steps for the smallest eigenvalue of Q
     lanczos_iters: int = 100
     gamma_override: float = 0.0
@@ -781,6 +784,9 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
             z = x_new.copy()
             eps_ak *= st.rho_z
             eps_rk *= st.rho_z
+            if st.center_floor:
+                eps_ak = max(eps_ak, st.eps_abs)
+                eps_rk = max(eps_rk, st.eps_rel)
         x = x_new
         state = None
         if time.monotonic() > deadline:

@@ -120,6 +120,7 @@ void pdnqp_default_settings(pdnqp_settings *s) {
   s->sigma0_min = 1e-4;
   s->sigma0_max = 1e4;
   s->penalty_gate = 1;
+  s->center_floor = 1;
   s->lanczos_iters = 100;
   s->gamma_override = 0.0;
   s->step_boost = 1.0;

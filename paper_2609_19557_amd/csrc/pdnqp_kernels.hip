@@ -21,6 +21,11 @@ namespace pdnqp {
 namespace {
 
 constexpr int kWaves = kBlock / 64;
+constexpr int kDecideThreads = 1024;
+// slots of the reduction buffer used by the per-trial kernels
+constexpr int PS_X = 0;    // x trial: sum dx^2 / taub_x
+constexpr int PS_ROW = 1;  // rows (4 slots)
+constexpr int PS_AT = 5;   // A' kernel (2 slots)
 
 __device__ __forceinline__ double clampd(double v, double lo, double hi) {
   // NaN propagates (comparisons with NaN are false), like numpy.clip.
@@ -150,6 +155,61 @@ __device__ __forceinline__ void for_elems(int n, int b, int nb, F &&f) {
   for (int i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) f(i);
 }
 
+// CSR-stream row sums of rows [r0, r1) of M x.  The workgroup loads the
+// block's nonzeros with unit stride (kStreamE per thread, all independent),
+// gathers x for all of them at once, stages the products in LDS and lets
+// one thread per row add its products in order; f(row, sum) runs on that
+// thread.  A block holding a single row longer than a tile sums it with a
+// block reduction instead and calls f on thread 0.
+template <typename F>
+__device__ __forceinline__ void stream_rows(const Csr &M, const double *__restrict__ x, int r0,
+                                            int r1, double *__restrict__ sprod, F &&f) {
+  const int base = M.p[r0];
+  const int cnt = M.p[r1] - base;
+  if (cnt <= kTile) {
+    int col[kStreamE];
+    double val[kStreamE];
+#pragma unroll
+    for (int e = 0; e < kStreamE; ++e) {
+      const int k = e * kBlock + threadIdx.x;
+      col[e] = 0;
+      val[e] = 0.0;
+      if (k < cnt) {
+        col[e] = __builtin_nontemporal_load(&M.i[base + k]);
+        val[e] = __builtin_nontemporal_load(&M.v[base + k]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kStreamE; ++e) {
+      const int k = e * kBlock + threadIdx.x;
+      if (k < cnt) sprod[k] = val[e] * x[col[e]];
+    }
+    __syncthreads();
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
+      const int a = M.p[row] - base;
+      const int b = M.p[row + 1] - base;
+      double s = 0.0;
+      for (int k = a; k < b; ++k) s += sprod[k];
+      f(row, s);
+    }
+    __syncthreads();
+  } else {
+    __shared__ double red[kWaves];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < cnt; k += kBlock) s += M.v[base + k] * x[M.i[base + k]];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = red[0];
+      for (int w = 1; w < kWaves; ++w) t += red[w];
+      f(r0, t);
+    }
+    __syncthreads();
+  }
+}
+
 // Dispatch on the lanes-per-row template parameter.
 #define PDNQP_DISPATCH_G(G, ...)                        \
   switch (G) {                                          \
@@ -180,68 +240,72 @@ __global__ __launch_bounds__(kBlock) void k_xtrial(Ctrl *__restrict__ c, InnerPa
   const double *__restrict__ x = v.X[cur];
   const double *__restrict__ qx = v.QX[cur];
   const double *__restrict__ aty = v.ATY[cur];
+  const double *__restrict__ ql = v.qx;
+  const double *__restrict__ tbx = v.taub_x;
+  const double *__restrict__ lo = v.lo;
+  const double *__restrict__ hi = v.hi;
   double *__restrict__ xt = v.X[cur ^ 1];
   double *__restrict__ xbar = v.xbar;
   double *__restrict__ qxbar = v.qxbar;
+  constexpr int U = 4;
+  const int stride = gridDim.x * kBlock;
   double acc = 0.0;
-  for_elems(p.n, blockIdx.x, gridDim.x, [&](int i) {
-    const double xi = x[i];
-    const double qxi = qx[i];
-    double xb = xbar[i];
-    double qb = qxbar[i];
-    if (pend) {
-      xb = (1.0 - ap) * xb + ap * xi;
-      qb = (1.0 - ap) * qb + ap * qxi;
-      xbar[i] = xb;
-      qxbar[i] = qb;
+  for (int i0 = blockIdx.x * kBlock + threadIdx.x; i0 < p.n; i0 += U * stride) {
+    double xi[U], qxi[U], xb[U], qb[U], ay[U], qv[U], tb[U], l[U], h[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * stride;
+      if (i < p.n) {
+        xi[u] = x[i]; qxi[u] = qx[i]; xb[u] = xbar[i]; qb[u] = qxbar[i]; ay[u] = aty[i];
+        qv[u] = ql[i]; tb[u] = tbx[i]; l[u] = lo[i]; h[u] = hi[i];
+      }
     }
-    const double hx = qxi + gi * xi;
-    const double hb = qb + gi * xb;
-    const double g = v.qx[i] + (1.0 - alpha) * hb + alpha * hx - aty[i];
-    const double tb = v.taub_x[i];
-    const double xn = clampd(xi - (sct * tb) * g, v.lo[i], v.hi[i]);
-    xt[i] = xn;
-    const double d = xn - xi;
-    acc += d * d / tb;
-  });
-  double vals[1] = {acc};
-  block_reduce<1>(vals, 0u, v.partial, blockIdx.x);
-  if (last_block(&c->ticket[TK_XTRIAL], gridDim.x)) {
-    double res[1];
-    final_reduce<1>(v.partial, gridDim.x, 0u, res);
-    if (threadIdx.x == 0) {
-      c->sum_x = res[0];
-      c->ticket[TK_XTRIAL] = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * stride;
+      if (i < p.n) {
+        double xbu = xb[u], qbu = qb[u];
+        if (pend) {
+          xbu = (1.0 - ap) * xbu + ap * xi[u];
+          qbu = (1.0 - ap) * qbu + ap * qxi[u];
+          xbar[i] = xbu;
+          qxbar[i] = qbu;
+        }
+        const double hx = qxi[u] + gi * xi[u];
+        const double hb = qbu + gi * xbu;
+        const double g = qv[u] + (1.0 - alpha) * hb + alpha * hx - ay[u];
+        const double xn = clampd(xi[u] - (sct * tb[u]) * g, l[u], h[u]);
+        xt[i] = xn;
+        const double d = xn - xi[u];
+        acc += d * d / tb[u];
+      }
     }
   }
+  double vals[1] = {acc};
+  block_reduce<1>(vals, 0u, v.partial + PS_X * kMaxParts, blockIdx.x);
 }
 
 // ===========================================================================
-// Trial step, sparse part 1 (one launch, two row partitions):
-//  * rows of Q:   Q x_tr                               (H w_tr, x block)
-//  * rows of A:   A x_tr, then row-locally (eq. (pdqp-trial)):
-//      s_tr = max(b_I, s - tau_s y_I)                  (s block: gradient y_I)
-//      r_tr = r - tau_r ((1-a) sigma rbar + a sigma r + lambda + y)
-//      (B w_tr)_j = (A x_tr)_j - [s_tr] - r_tr
-//      y_tr = y + eta (h - B w_tr - beta (B w_tr - B w))
-//    plus the previous accept's averaging of ybar, rbar, sbar and the
-//    row-block parts of the acceptance sums.
+// Trial step, sparse part 1, CSR-stream form (one launch, two partitions):
+// row blocks of Q (Q x_tr) and of A (A x_tr with the row-local s/r/y trial,
+// the previous accept's averaging of ybar, rbar, sbar and the row-block
+// acceptance sums).  Same arithmetic as the row-group form below.
 // ===========================================================================
-template <int GQ, int GA>
-__global__ __launch_bounds__(kBlock) void k_qa(Ctrl *__restrict__ c, InnerParams p, Vecs v, Csr Q,
-                                               Csr A, Part pq, Part pa) {
+__global__ __launch_bounds__(kBlock) void k_qa_stream(Ctrl *__restrict__ c, InnerParams p,
+                                                      Vecs v, Csr Q, Csr A, int gq, int ga) {
   if (c->state != ST_RUNNING) return;
+  __shared__ double sprod[kTile];
   const int cur = c->cur;
   const int nxt = cur ^ 1;
   const double *__restrict__ xt = v.X[nxt];
-  if ((int)blockIdx.x < pq.blocks) {
+  if ((int)blockIdx.x < gq) {
     double *__restrict__ qxt = v.QX[nxt];
-    for_rows<GQ>(Q.rows, blockIdx.x, pq.blocks, [&](int row, int lane) {
-      const double s = row_dot<GQ>(Q.p, Q.i, Q.v, xt, row, lane);
-      if (lane == 0) qxt[row] = s;
-    });
+    const double *__restrict__ qd = v.qdiag;
+    for (int rb = blockIdx.x; rb < Q.nrb; rb += gq)
+      stream_rows(Q, xt, Q.rb[rb], Q.rb[rb + 1], sprod,
+                  [&](int row, double s) { qxt[row] = s + qd[row] * xt[row]; });
   } else {
-    const int b = blockIdx.x - pq.blocks;
+    const int b = blockIdx.x - gq;
     const int pend = c->pending;
     const double ap = c->alpha_pend;
     const double Nd = (double)c->N;
@@ -251,50 +315,41 @@ __global__ __launch_bounds__(kBlock) void k_qa(Ctrl *__restrict__ c, InnerParams
     const double scy = c->step_scale * c->omega;
     const int me = p.me;
     double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-    for_rows<GA>(A.rows, b, pa.blocks, [&](int j, int lane) {
-      const double ax = row_dot<GA>(A.p, A.i, A.v, xt, j, lane);
-      const bool w0 = (lane == 0);
-      const double y = v.Y[cur][j];
-      const double bw = v.BW[cur][j];
-      const double r = v.R[cur][j];
-      const double sg = v.sigma[j];
-      const double lm = v.lam[j];
-      const double bj = v.b[j];
-      double yb = v.ybar[j];
-      double rb = v.rbar[j];
-      if (pend) {
-        yb = (1.0 - ap) * yb + ap * y;
-        rb = (1.0 - ap) * rb + ap * r;
-        if (w0) {
-          v.ybar[j] = yb;
-          v.rbar[j] = rb;
-        }
-      }
-      const double gr = (1.0 - alpha) * (sg * rb) + alpha * (sg * r) + lm + y;
-      const double tbr = v.taub_r[j];
-      const double rt = r - (sct * tbr) * gr;
-      double bwt, hj, ds = 0.0, ds2t = 0.0;
-      if (j < me) {
-        bwt = ax - rt;
-        hj = bj;
-      } else {
-        const int k = j - me;
-        const double s = v.S[cur][k];
+    for (int rb = b; rb < A.nrb; rb += ga) {
+      stream_rows(A, xt, A.rb[rb], A.rb[rb + 1], sprod, [&](int j, double ax) {
+        const double y = v.Y[cur][j];
+        const double bw = v.BW[cur][j];
+        const double r = v.R[cur][j];
+        const double sg = v.sigma[j];
+        const double lm = v.lam[j];
+        const double bj = v.b[j];
+        double rb_ = v.rbar[j];
         if (pend) {
-          const double sb = (1.0 - ap) * v.sbar[k] + ap * s;
-          if (w0) v.sbar[k] = sb;
+          v.ybar[j] = (1.0 - ap) * v.ybar[j] + ap * y;
+          rb_ = (1.0 - ap) * rb_ + ap * r;
+          v.rbar[j] = rb_;
         }
-        const double tbs = v.taub_s[k];
-        const double st = maxd(s - (sct * tbs) * y, bj);
-        if (w0) v.S[nxt][k] = st;
-        bwt = ax - st - rt;
-        hj = 0.0;
-        ds = st - s;
-        ds2t = ds * ds / tbs;
-      }
-      const double eb = v.etab[j];
-      const double yt = y + (scy * eb) * (hj - bwt - beta * (bwt - bw));
-      if (w0) {
+        const double gr = (1.0 - alpha) * (sg * rb_) + alpha * (sg * r) + lm + y;
+        const double tbr = v.taub_r[j];
+        const double rt = r - (sct * tbr) * gr;
+        double bwt, hj, ds = 0.0, ds2t = 0.0;
+        if (j < me) {
+          bwt = ax - rt;
+          hj = bj;
+        } else {
+          const int k = j - me;
+          const double sv = v.S[cur][k];
+          if (pend) v.sbar[k] = (1.0 - ap) * v.sbar[k] + ap * sv;
+          const double tbs = v.taub_s[k];
+          const double st = maxd(sv - (sct * tbs) * y, bj);
+          v.S[nxt][k] = st;
+          bwt = ax - st - rt;
+          hj = 0.0;
+          ds = st - sv;
+          ds2t = ds * ds / tbs;
+        }
+        const double eb = v.etab[j];
+        const double yt = y + (scy * eb) * (hj - bwt - beta * (bwt - bw));
         v.R[nxt][j] = rt;
         v.BW[nxt][j] = bwt;
         v.Y[nxt][j] = yt;
@@ -304,96 +359,140 @@ __global__ __launch_bounds__(kBlock) void k_qa(Ctrl *__restrict__ c, InnerParams
         s2 += dy * dy / eb;
         s3 += fabs(dr * (sg * dr));
         s4 += fabs(dr * dy) + fabs(ds * dy);
-      }
-    });
-    double vals[4] = {s1, s2, s3, s4};
-    block_reduce<4>(vals, 0u, v.partial, b);
-  }
-  if (last_block(&c->ticket[TK_QA], gridDim.x)) {
-    double res[4];
-    final_reduce<4>(v.partial, pa.blocks, 0u, res);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < 4; ++k) c->sum_row[k] = res[k];
-      c->ticket[TK_QA] = 0;
+      });
     }
+    double vals[4] = {s1, s2, s3, s4};
+    block_reduce<4>(vals, 0u, v.partial + PS_ROW * kMaxParts, b);
   }
 }
 
-// ===========================================================================
-// Trial step, sparse part 2: rows of A' (B' y_tr, x block), the x-block
-// parts of the acceptance sums |dx (H dx)| and |dx (A' dy)|, and -- in the
-// last workgroup -- the acceptance test (adaptive-condition) with its
-// consequences: accept (swap buffers, count, schedule the averaging) or
-// reject (shrink both steps by a common factor, count, give up after the
-// rejection limit).
-// ===========================================================================
-template <int GT>
-__global__ __launch_bounds__(kBlock) void k_at(Ctrl *__restrict__ c, InnerParams p, Vecs v,
-                                               Csr AT, Part pt) {
+// Decision of the acceptance test (adaptive-condition) from the three
+// kernels' sums; run by one thread.  All control-block fields are loaded
+// first (one batch of independent loads) and written back at the end.
+__device__ void accept_decision(Ctrl *__restrict__ c, const InnerParams &p, const Vecs &v,
+                                double sx, const double (&sr)[4], double sum_hdx,
+                                double sum_bdy) {
+  const int cur = c->cur;
+  const int N = c->N, t = c->t, t_call = c->t_call, rejects = c->rejects;
+  const int ntr = c->trace_trials_n;
+  const double sc = c->step_scale;
+  const double om = c->omega;
+  const int64_t trials = c->trials, accepted = c->accepted, rejected = c->rejected;
+  const double L = 0.5 * ((om / sc) * (sx + sr[0]) + sr[1] / (sc * om));
+  const double R = 0.5 * (sum_hdx + sr[2]) + (sum_bdy + sr[3]);
+  c->sum_x = sx;
+  for (int k = 0; k < 4; ++k) c->sum_row[k] = sr[k];
+  c->L = L;
+  c->R = R;
+  c->trials = trials + 1;
+  const bool finite = isfinite(L) && isfinite(R);
+  const bool acc = finite && (L >= R);
+  if (ntr < p.trace_trials_cap) {
+    v.trace_tr[3 * ntr + 0] = L;
+    v.trace_tr[3 * ntr + 1] = R;
+    v.trace_tr[3 * ntr + 2] = acc ? 1.0 : 0.0;
+    c->trace_trials_n = ntr + 1;
+  }
+  c->last_acc = acc ? 1 : 0;
+  if (!finite) {
+    c->state = ST_NUMERR;
+    c->pending = 0;
+  } else if (acc) {
+    c->alpha_pend = 2.0 / ((double)N + 2.0);
+    c->pending = 1;
+    c->cur = cur ^ 1;
+    c->N = N + 1;
+    c->t = t + 1;
+    c->t_call = t_call + 1;
+    c->rejects = 0;
+    c->accepted = accepted + 1;
+    if (((t + 1) % p.check_every) == 0 || t_call + 1 >= p.max_inner) c->state = ST_CHECK_DUE;
+  } else {
+    double kappa = p.shrink_safety * L / R;
+    kappa = kappa < p.shrink_min ? p.shrink_min : (kappa > p.shrink_max ? p.shrink_max : kappa);
+    c->step_scale = kappa * sc;
+    c->pending = 0;
+    c->rejects = rejects + 1;
+    c->rejected = rejected + 1;
+    if (rejects + 1 >= p.max_rejects) c->state = ST_NUMERR;
+  }
+}
+
+// Trial step, sparse part 2, CSR-stream form: row blocks of A' (A' y_tr),
+// the x-block acceptance sums, and the decision in the last workgroup.
+__global__ __launch_bounds__(kBlock) void k_at_stream(Ctrl *__restrict__ c, InnerParams p,
+                                                      Vecs v, Csr AT) {
   if (c->state != ST_RUNNING) return;
+  __shared__ double sprod[kTile];
   const int cur = c->cur;
   const int nxt = cur ^ 1;
   const double gi = p.gamma_inv;
   const double *__restrict__ yt = v.Y[nxt];
   double s5 = 0.0, s6 = 0.0;
-  for_rows<GT>(AT.rows, blockIdx.x, gridDim.x, [&](int i, int lane) {
-    const double a = row_dot<GT>(AT.p, AT.i, AT.v, yt, i, lane);
-    if (lane == 0) {
+  for (int rb = blockIdx.x; rb < AT.nrb; rb += gridDim.x) {
+    stream_rows(AT, yt, AT.rb[rb], AT.rb[rb + 1], sprod, [&](int i, double a) {
       v.ATY[nxt][i] = a;
       const double dx = v.X[nxt][i] - v.X[cur][i];
       const double hdx = (v.QX[nxt][i] - v.QX[cur][i]) + gi * dx;
       const double ady = a - v.ATY[cur][i];
       s5 += fabs(dx * hdx);
       s6 += fabs(dx * ady);
-    }
-  });
+    });
+  }
   double vals[2] = {s5, s6};
-  block_reduce<2>(vals, 0u, v.partial, blockIdx.x);
-  if (last_block(&c->ticket[TK_AT], gridDim.x)) {
-    double res[2];
-    final_reduce<2>(v.partial, gridDim.x, 0u, res);
-    if (threadIdx.x == 0) {
-      c->ticket[TK_AT] = 0;
-      const double sc = c->step_scale;
-      const double om = c->omega;
-      const double L = 0.5 * ((om / sc) * (c->sum_x + c->sum_row[0]) + c->sum_row[1] / (sc * om));
-      const double R = 0.5 * (res[0] + c->sum_row[2]) + (res[1] + c->sum_row[3]);
-      c->L = L;
-      c->R = R;
-      c->trials += 1;
-      const bool finite = isfinite(L) && isfinite(R);
-      const bool acc = finite && (L >= R);
-      if (c->trace_trials_n < p.trace_trials_cap) {
-        const int k = c->trace_trials_n;
-        v.trace_tr[3 * k + 0] = L;
-        v.trace_tr[3 * k + 1] = R;
-        v.trace_tr[3 * k + 2] = acc ? 1.0 : 0.0;
-        c->trace_trials_n = k + 1;
-      }
-      c->last_acc = acc ? 1 : 0;
-      if (!finite) {
-        c->state = ST_NUMERR;
-        c->pending = 0;
-      } else if (acc) {
-        c->alpha_pend = 2.0 / ((double)c->N + 2.0);
-        c->pending = 1;
-        c->cur = nxt;
-        c->N += 1;
-        c->t += 1;
-        c->t_call += 1;
-        c->rejects = 0;
-        c->accepted += 1;
-        if ((c->t % p.check_every) == 0 || c->t_call >= p.max_inner) c->state = ST_CHECK_DUE;
-      } else {
-        double kappa = p.shrink_safety * L / R;
-        kappa = kappa < p.shrink_min ? p.shrink_min : (kappa > p.shrink_max ? p.shrink_max : kappa);
-        c->step_scale = kappa * sc;
-        c->pending = 0;
-        c->rejects += 1;
-        c->rejected += 1;
-        if (c->rejects >= p.max_rejects) c->state = ST_NUMERR;
-      }
+  block_reduce<2>(vals, 0u, v.partial + PS_AT * kMaxParts, blockIdx.x);
+}
+
+// Acceptance test of the trial: one workgroup adds the partials of the three
+// trial kernels in a fixed order (the kernel boundaries order their writes;
+// no fences are needed) and takes the decision.
+__global__ __launch_bounds__(kDecideThreads) void k_decide(Ctrl *__restrict__ c, InnerParams p,
+                                                           Vecs v, int gx, int ga, int gt) {
+  const int state = c->state;
+  const double *part = v.partial;
+  double a[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) a[k] = 0.0;
+  // all loads of this thread are independent (one batch of up to 28)
+  constexpr int PER = kMaxParts / kDecideThreads;
+  double lx[PER], lr[PER][4], lt[PER][2];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = threadIdx.x + j * kDecideThreads;
+    lx[j] = i < gx ? part[PS_X * kMaxParts + i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lr[j][k] = i < ga ? part[(PS_ROW + k) * kMaxParts + i] : 0.0;
+    lt[j][0] = i < gt ? part[PS_AT * kMaxParts + i] : 0.0;
+    lt[j][1] = i < gt ? part[(PS_AT + 1) * kMaxParts + i] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    a[0] += lx[j];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[1 + k] += lr[j][k];
+    a[5] += lt[j][0];
+    a[6] += lt[j][1];
+  }
+  if (state != ST_RUNNING) return;
+  __shared__ double sh[kDecideThreads / 64][7];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    double x = a[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sh[wid][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[7];
+    for (int k = 0; k < 7; ++k) {
+      double acc = sh[0][k];
+      for (int w = 1; w < kDecideThreads / 64; ++w) acc += sh[w][k];
+      r[k] = acc;
     }
+    const double sr[4] = {r[1], r[2], r[3], r[4]};
+    accept_decision(c, p, v, r[0], sr, r[5], r[6]);
   }
 }
 
@@ -453,10 +552,6 @@ __global__ __launch_bounds__(kBlock) void k_flush(Ctrl *__restrict__ c, InnerPar
         v.sbar[k] = (1.0 - ap) * v.sbar[k] + ap * v.S[cur][k];
       }
     });
-  }
-  if (last_block(&c->ticket[TK_FLUSH], gridDim.x) && threadIdx.x == 0) {
-    c->pending = 0;
-    c->ticket[TK_FLUSH] = 0;
   }
 }
 
@@ -582,11 +677,48 @@ __global__ __launch_bounds__(kBlock) void k_check(Ctrl *__restrict__ c, InnerPar
     });
   }
   block_reduce<CK_N>(a, kChkMaxMask, v.partial, blockIdx.x);
-  if (!last_block(&c->ticket[TK_CHECK], gridDim.x)) return;
-  double r[CK_N];
-  final_reduce<CK_N>(v.partial, gridDim.x, kChkMaxMask, r);
+}
+
+// Decision of a check: one workgroup combines k_check's partials in a fixed
+// order, then (thread 0) the stopping test, candidate choice, restart rule
+// and primal-weight update.
+__global__ __launch_bounds__(kDecideThreads) void k_check_decide(Ctrl *__restrict__ c,
+                                                                 InnerParams p, Vecs v,
+                                                                 int nparts) {
+  if (c->state != ST_CHECK_DUE) return;
+  double a[CK_N];
+#pragma unroll
+  for (int k = 0; k < CK_N; ++k) a[k] = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kDecideThreads) {
+#pragma unroll
+    for (int k = 0; k < CK_N; ++k) {
+      const double x = v.partial[k * kMaxParts + i];
+      a[k] = ((kChkMaxMask >> k) & 1u) ? fmax(a[k], x) : a[k] + x;
+    }
+  }
+  __shared__ double sh[kDecideThreads / 64][CK_N];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < CK_N; ++k) {
+    double x = a[k];
+    const bool mx = (kChkMaxMask >> k) & 1u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_down(x, off, 64);
+      x = mx ? fmax(x, o) : x + o;
+    }
+    if (lane == 0) sh[wid][k] = x;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  c->ticket[TK_CHECK] = 0;
+  double r[CK_N];
+  for (int k = 0; k < CK_N; ++k) {
+    const bool mx = (kChkMaxMask >> k) & 1u;
+    double acc = sh[0][k];
+    for (int w = 1; w < kDecideThreads / 64; ++w) acc = mx ? fmax(acc, sh[w][k]) : acc + sh[w][k];
+    r[k] = acc;
+  }
+  c->pending = 0;  // the averages were brought up to date by k_flush
   for (int k = 0; k < CK_N; ++k) c->chk[k] = r[k];
   const double om = c->omega;
   const double k0 = sqrt(om * om * r[CK_P] + r[CK_D] / (om * om));
@@ -709,11 +841,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(Ctrl *__restrict__ c, InnerPar
       }
     });
   }
-  if (last_block(&c->ticket[TK_APPLY], gridDim.x) && threadIdx.x == 0) {
-    c->copy_avg = 0;
-    c->restart_flag = 0;
-    c->ticket[TK_APPLY] = 0;
-  }
+}
+
+// Clears the flags k_apply acted on (one thread, after k_apply).
+__global__ void k_apply_done(Ctrl *__restrict__ c) {
+  c->copy_avg = 0;
+  c->restart_flag = 0;
 }
 
 // ===========================================================================
@@ -1165,6 +1298,7 @@ __global__ __launch_bounds__(kBlock) void k_elem(int op, double *a, const double
       case EL_SCALE_DIV: a[i] = s * b[i] / c[i]; break;
       case EL_NEG: a[i] = -b[i]; break;
       case EL_AXPBY: a[i] = b[i] / s; break;
+      case EL_DIAG: a[i] = s * ((b[i] * c[i]) * b[i]); break;
       default: a[i] = a[i] / b[i]; break;
     }
   });
@@ -1198,26 +1332,51 @@ Part make_part(int32_t rows, int32_t G, int32_t max_blocks) {
 
 static inline int nz(int b) { return b > 0 ? b : 1; }
 
+static inline int xtrial_blocks(int n) {
+  return nz((int)std::min<int64_t>(((int64_t)n + 4 * kBlock - 1) / (4 * kBlock), kMaxParts));
+}
+
 void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px) {
-  hipLaunchKernelGGL(k_xtrial, dim3(nz(px.blocks)), dim3(kBlock), 0, st, c, p, v, px);
+  hipLaunchKernelGGL(k_xtrial, dim3(xtrial_blocks(p.n)), dim3(kBlock), 0, st, c, p, v, px);
+}
+
+void stream_row_blocks(const int32_t *rp, int32_t rows, int32_t max_rows, int32_t *out_nrb,
+                       int32_t *rb) {
+  int32_t nb = 0;
+  rb[0] = 0;
+  int32_t r = 0;
+  while (r < rows) {
+    const int32_t start = r;
+    const int32_t base = rp[r];
+    ++r;
+    while (r < rows && rp[r + 1] - base <= kTile && r - start < max_rows) ++r;
+    rb[++nb] = r;
+  }
+  *out_nrb = nb;
 }
 
 void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &Q,
                const Csr &A, const Part &pq, const Part &pa) {
-  const int grid = pq.blocks + pa.blocks;
-  PDNQP_DISPATCH_G(Q.G, {
-    constexpr int GQ_ = GV;
-    PDNQP_DISPATCH_G(A.G, {
-      hipLaunchKernelGGL((k_qa<GQ_, GV>), dim3(nz(grid)), dim3(kBlock), 0, st, c, p, v, Q, A, pq, pa);
-    });
-  });
+  (void)pq;
+  (void)pa;
+  const int gq = std::min(Q.nrb, kMaxParts);
+  const int ga = std::min(A.nrb, kMaxParts);
+  hipLaunchKernelGGL(k_qa_stream, dim3(nz(gq + ga)), dim3(kBlock), 0, st, c, p, v, Q, A, gq, ga);
 }
 
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &AT,
                const Part &pt) {
-  PDNQP_DISPATCH_G(AT.G, {
-    hipLaunchKernelGGL((k_at<GV>), dim3(nz(pt.blocks)), dim3(kBlock), 0, st, c, p, v, AT, pt);
-  });
+  (void)pt;
+  const int g = std::min(AT.nrb, kMaxParts);
+  hipLaunchKernelGGL(k_at_stream, dim3(nz(g)), dim3(kBlock), 0, st, c, p, v, AT);
+}
+
+void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &A,
+                   const Csr &AT) {
+  const int gx = xtrial_blocks(p.n);
+  const int ga = std::min(A.nrb, kMaxParts);
+  const int gt = nz(std::min(AT.nrb, kMaxParts));
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideThreads), 0, st, c, p, v, gx, ga, gt);
 }
 
 void launch_trace(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
@@ -1248,14 +1407,16 @@ void launch_check_spmv(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs
 
 void launch_check(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
                   const Part &ps, const Part &pr) {
-  hipLaunchKernelGGL(k_check, dim3(nz(px.blocks + ps.blocks + pr.blocks)), dim3(kBlock), 0, st,
-                     c, p, v, px, ps, pr);
+  const int g = nz(px.blocks + ps.blocks + pr.blocks);
+  hipLaunchKernelGGL(k_check, dim3(g), dim3(kBlock), 0, st, c, p, v, px, ps, pr);
+  hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kDecideThreads), 0, st, c, p, v, g);
 }
 
 void launch_apply(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
                   const Part &pr) {
   hipLaunchKernelGGL(k_apply, dim3(nz(px.blocks + pr.blocks)), dim3(kBlock), 0, st, c, p, v, px,
                      pr);
+  hipLaunchKernelGGL(k_apply_done, dim3(1), dim3(1), 0, st, c);
 }
 
 void launch_inner_init(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,

@@ -18,7 +18,9 @@
 namespace pdnqp {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
-constexpr int kMaxParts = 1024;    // upper bound of reduction partials per part
+constexpr int kMaxParts = 4096;    // upper bound of reduction partials per launch
+constexpr int kStreamE = 8;        // CSR-stream: nonzeros per thread per row block
+constexpr int kTile = kStreamE * kBlock;  // CSR-stream: nonzeros per row block (2048)
 
 enum State : int32_t {
   ST_RUNNING = 0,
@@ -94,13 +96,23 @@ struct Csr {
   const int32_t *i;
   const double *v;
   int32_t rows;
-  int32_t G;           // lanes per row (power of two, 2..32)
+  int32_t G;           // lanes per row (power of two, 2..32) of the row-group kernels
+  const int32_t *rb;   // CSR-stream row blocks: block b owns rows [rb[b], rb[b+1])
+  int32_t nrb;         // number of row blocks
+  int32_t pad;
 };
+
+// Row blocks for the CSR-stream kernels: consecutive rows whose nonzeros fit
+// in one tile of kTile entries (a longer row gets a block of its own), at
+// most max_rows rows per block.
+void stream_row_blocks(const int32_t *rp, int32_t rows, int32_t max_rows, int32_t *out_nrb,
+                       int32_t *rb /* capacity rows + 1 */);
 
 // Every device vector the kernels touch, passed by value.
 struct Vecs {
   // outer-scaled problem data
   const double *c, *lo, *hi, *b;   // b: b_E on equality rows, b_I on inequality rows
+  const double *qdiag;             // diagonal of the scaled Q (the hot Q product uses Q without it)
   // inner QP of the current outer step
   double *sigma, *lam, *z, *qx;    // qx = c - z / gamma
   double *taub_x, *taub_s, *taub_r, *etab;  // steps without omega and shrink factor
@@ -132,10 +144,14 @@ Part make_part(int32_t rows, int32_t G, int32_t max_blocks);
 
 // ---- per-trial kernels -----------------------------------------------------
 void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px);
+// Q: the off-diagonal part of Q (its diagonal is v.qdiag)
 void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &Q,
                const Csr &A, const Part &pq, const Part &pa);
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &AT,
                const Part &pt);
+// acceptance test of the trial (one workgroup), after launch_at
+void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &A,
+                   const Csr &AT);
 void launch_trace(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
                   const Part &pr);
 
@@ -181,7 +197,7 @@ void launch_row_abssum(hipStream_t st, const Csr &M, double *out, const Part &pm
 void launch_ruiz_update(hipStream_t st, double *Dc, const double *rn, int32_t m, double *Dx,
                         const double *cn, const double *cnq, int32_t n);
 enum ElemOp : int { EL_GRAD = 0, EL_MULS = 1, EL_DIV = 2, EL_MUL = 3, EL_SCALE_DIV = 4,
-                    EL_NEG = 5, EL_AXPBY = 6, EL_DIVINTO = 7 };
+                    EL_NEG = 5, EL_AXPBY = 6, EL_DIVINTO = 7, EL_DIAG = 8 };
 void launch_elem(hipStream_t st, int op, double *a, const double *b, const double *c, double s,
                  int32_t n);
 // out[j] = A x0 - P_C(A x0) from v.ax

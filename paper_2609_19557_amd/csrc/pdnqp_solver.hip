@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 
@@ -72,7 +73,7 @@ double ninf(const std::vector<double> &v) {
   return m;
 }
 
-enum TimerId { TM_XTRIAL = 0, TM_QA = 1, TM_AT = 2, TM_COUNT = 3 };
+enum TimerId { TM_XTRIAL = 0, TM_QA = 1, TM_AT = 2, TM_DECIDE = 3, TM_COUNT = 4 };
 
 }  // namespace
 
@@ -144,6 +145,25 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   Ap_ = I(m + 1); Ai_ = I(nza); Araw_ = D(nza); Av_ = D(nza);
   ATp_ = I(n + 1); ATi_ = I(nza); ATraw_ = D(nza); ATv_ = D(nza);
   atperm_ = I(nza);
+  // off-diagonal part of Q for the hot product, diagonal kept as a vector
+  {
+    qp_.Qop.assign(n + 1, 0);
+    qp_.Qdiag.assign(n, 0.0);
+    for (int32_t i = 0; i < n; ++i) {
+      for (int32_t k = qp_.Qp[i]; k < qp_.Qp[i + 1]; ++k) {
+        if (qp_.Qi[k] == i) {
+          qp_.Qdiag[i] = qp_.Qx[k];
+        } else {
+          qp_.Qoi.push_back(qp_.Qi[k]);
+          qp_.Qox.push_back(qp_.Qx[k]);
+        }
+      }
+      qp_.Qop[i + 1] = (int32_t)qp_.Qoi.size();
+    }
+  }
+  const int64_t nzo = qp_.Qoi.size();
+  Qop_ = I(n + 1); Qoi_ = I(nzo); Qoraw_ = D(nzo); Qov_ = D(nzo);
+  qdiag_raw_ = D(n); qdiag_ = D(n);
   craw_ = D(n); xlraw_ = D(n); xuraw_ = D(n); braw_ = D(m);
   c_ = D(n); lo_ = D(n); hi_ = D(n); b_ = D(m);
   v_.c = c_; v_.lo = lo_; v_.hi = hi_; v_.b = b_;
@@ -184,6 +204,10 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   chain(H2D(ATi_, qp_.ATi.data(), nza * 4));
   chain(H2D(ATraw_, qp_.ATx.data(), nza * 8));
   chain(H2D(atperm_, qp_.ATperm.data(), nza * 4));
+  chain(H2D(Qop_, qp_.Qop.data(), (n + 1) * 4));
+  chain(H2D(Qoi_, qp_.Qoi.data(), nzo * 4));
+  chain(H2D(Qoraw_, qp_.Qox.data(), nzo * 8));
+  chain(H2D(qdiag_raw_, qp_.Qdiag.data(), n * 8));
   chain(H2D(craw_, qp_.c.data(), n * 8));
   chain(H2D(xlraw_, qp_.xl.data(), n * 8));
   chain(H2D(xuraw_, qp_.xu.data(), n * 8));
@@ -192,12 +216,32 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   if ((r = check(e, "upload", err))) return r;
 
   const int GQ = pick_G(nzq, n), GA = pick_G(nza, m), GT = pick_G(nza, n);
-  Q_ = Csr{Qp_, Qi_, Qv_, n, GQ};
-  A_ = Csr{Ap_, Ai_, Av_, m, GA};
-  AT_ = Csr{ATp_, ATi_, ATv_, n, GT};
-  Qr_ = Csr{Qp_, Qi_, Qraw_, n, GQ};
-  Ar_ = Csr{Ap_, Ai_, Araw_, m, GA};
-  ATr_ = Csr{ATp_, ATi_, ATraw_, n, GT};
+  // CSR-stream row blocks of the three matrices
+  auto blocks_of = [&](const std::vector<int32_t> &rp, int32_t rows, int32_t *&dev,
+                       int32_t &nrb) -> bool {
+    std::vector<int32_t> rb(rows + 2);
+    stream_row_blocks(rp.data(), rows, 4 * kBlock, &nrb, rb.data());
+    dev = (int32_t *)dalloc((size_t)(nrb + 1) * 4);
+    if (!dev) return false;
+    return hipMemcpyAsync(dev, rb.data(), (size_t)(nrb + 1) * 4, hipMemcpyHostToDevice,
+                          stream_) == hipSuccess;
+  };
+  int32_t *qrb = nullptr, *arb = nullptr, *atrb = nullptr, *qorb = nullptr;
+  int32_t nq = 0, na = 0, nt = 0, nqo = 0;
+  if (!blocks_of(qp_.Qp, n, qrb, nq) || !blocks_of(qp_.Ap, m, arb, na) ||
+      !blocks_of(qp_.ATp, n, atrb, nt) || !blocks_of(qp_.Qop, n, qorb, nqo)) {
+    err = "row-block upload failed";
+    return PDNQP_E_DEVICE;
+  }
+  if ((r = check(hipStreamSynchronize(stream_), "row-block upload", err))) return r;
+  Q_ = Csr{Qp_, Qi_, Qv_, n, GQ, qrb, nq, 0};
+  Qo_ = Csr{Qop_, Qoi_, Qov_, n, pick_G(nzo, n), qorb, nqo, 0};
+  v_.qdiag = qdiag_;
+  A_ = Csr{Ap_, Ai_, Av_, m, GA, arb, na, 0};
+  AT_ = Csr{ATp_, ATi_, ATv_, n, GT, atrb, nt, 0};
+  Qr_ = Csr{Qp_, Qi_, Qraw_, n, GQ, qrb, nq, 0};
+  Ar_ = Csr{Ap_, Ai_, Araw_, m, GA, arb, na, 0};
+  ATr_ = Csr{ATp_, ATi_, ATraw_, n, GT, atrb, nt, 0};
   px_ = make_part(n, 1, 512);
   ps_ = make_part(mi, 1, 256);
   pr_ = make_part(m, 1, 256);
@@ -209,17 +253,21 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   timers_.resize(TM_COUNT);
   timers_[TM_XTRIAL].name = "xtrial";
   timers_[TM_QA].name = "qa_spmv";
-  timers_[TM_AT].name = "at_spmv_accept";
+  timers_[TM_AT].name = "at_spmv";
+  timers_[TM_DECIDE].name = "decide";
   const double me = qp_.me;
   timers_[TM_XTRIAL].bytes = 12.0 * 8.0 * n;
-  timers_[TM_QA].bytes = 12.0 * nzq + 4.0 * (n + 1) + 16.0 * n + 12.0 * nza + 4.0 * (m + 1) +
+  // Q part: off-diagonal values+indices, row pointers, x_tr once, diagonal, Q x_tr written;
+  // A part: values+indices, row pointers, x_tr once, row-local vectors
+  timers_[TM_QA].bytes = 12.0 * nzo + 4.0 * (n + 1) + 24.0 * n + 12.0 * nza + 4.0 * (m + 1) +
                          8.0 * n + 15.0 * 8.0 * me + 20.0 * 8.0 * mi;
   timers_[TM_AT].bytes = 12.0 * nza + 4.0 * (n + 1) + 8.0 * m + 8.0 * n + 5.0 * 8.0 * n;
+  timers_[TM_DECIDE].bytes = 0.0;
   return PDNQP_OK;
 }
 
 void Solver::timed_launch(int which, const std::function<void()> &f) {
-  if (!st_.profile) {
+  if (!sample_now_) {
     f();
     return;
   }
@@ -330,6 +378,10 @@ int Solver::setup(const double *x0c, const double *lam0_int, double &c_obj, doub
   hipMemcpyAsync(Qv_, Qraw_, Q_.rows ? qp_.Qi.size() * 8 : 0, hipMemcpyDeviceToDevice, stream_);
   hipMemcpyAsync(Av_, Araw_, qp_.Ai.size() * 8, hipMemcpyDeviceToDevice, stream_);
   launch_scale_csr(stream_, Qp_, Qi_, Qv_, n, v_.Dx, v_.Dx, c_obj, pq_);
+  if (!qp_.Qoi.empty())
+    hipMemcpyAsync(Qov_, Qoraw_, qp_.Qoi.size() * 8, hipMemcpyDeviceToDevice, stream_);
+  launch_scale_csr(stream_, Qop_, Qoi_, Qov_, n, v_.Dx, v_.Dx, c_obj, make_part(n, Qo_.G, 1024));
+  launch_elem(stream_, EL_DIAG, qdiag_, v_.Dx, qdiag_raw_, c_obj, n);
   launch_scale_csr(stream_, Ap_, Ai_, Av_, m, v_.Dc, v_.Dx, 1.0, pa_);
   launch_gather(stream_, ATv_, Av_, atperm_, (int64_t)qp_.Ai.size());
   launch_elem(stream_, EL_MULS, c_, v_.Dx, craw_, c_obj, n);
@@ -407,12 +459,15 @@ int Solver::run_inner(double deadline, std::string &err) {
   for (;;) {
     const int t = hctrl_->t, tc = hctrl_->t_call;
     int slots = st_.check_every - (t % st_.check_every);
+    sample_now_ = false;
     slots = std::min(slots, st_.max_inner - tc);
     slots = std::max(slots, 1);
     for (int s = 0; s < slots; ++s) {
+      sample_now_ = st_.profile > 0 && (slot_count_++ % st_.profile) == 0;
       timed_launch(TM_XTRIAL, [&] { launch_xtrial(stream_, ctrl_, ip_, v_, px_); });
-      timed_launch(TM_QA, [&] { launch_qa(stream_, ctrl_, ip_, v_, Q_, A_, pq_, pa_); });
+      timed_launch(TM_QA, [&] { launch_qa(stream_, ctrl_, ip_, v_, Qo_, A_, pq_, pa_); });
       timed_launch(TM_AT, [&] { launch_at(stream_, ctrl_, ip_, v_, AT_, pt_); });
+      timed_launch(TM_DECIDE, [&] { launch_decide(stream_, ctrl_, ip_, v_, A_, AT_); });
       if (trace_iters_cap_ > 0) launch_trace(stream_, ctrl_, ip_, v_, px_, pr_);
     }
     launch_flush(stream_, ctrl_, ip_, v_, px_, pr_);
@@ -562,6 +617,15 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     sd = std::max({1.0, ov[5], c_norm_, ov[6]});
     const double dxz = ov[7];
     const double rn = m ? ov[3] : 0.0;
+    if (st_.verbose) {
+      std::fprintf(stderr,
+                   "[pdnqp] outer %lld  r_p %.3e (tol %.3e)  r_d %.3e (tol %.3e)  inner %lld  "
+                   "restarts %lld  omega %.3g  delta %.2e  %.2fs\n",
+                   (long long)k, rp, eps_abs + eps_rel * sp, rd, eps_abs + eps_rel * sd,
+                   (long long)hctrl_->accepted, (long long)hctrl_->restarts, hctrl_->omega,
+                   delta_a, now_s() - t_start);
+      std::fflush(stderr);
+    }
     if (rp <= eps_abs + eps_rel * sp && rd <= eps_abs + eps_rel * sd) {
       status = PDNQP_SOLVED;
       break;
@@ -580,6 +644,10 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       launch_copy(stream_, v_.z, v_.X[hctrl_->cur], n);
       eps_ak *= st_.rho_z;
       eps_rk *= st_.rho_z;
+      if (st_.center_floor) {
+        eps_ak = std::max(eps_ak, eps_abs);
+        eps_rk = std::max(eps_rk, eps_rel);
+      }
     }
     need_form = true;
     if (now_s() > deadline) {

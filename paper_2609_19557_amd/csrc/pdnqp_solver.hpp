@@ -20,6 +20,8 @@ struct HostQP {
   int32_t n = 0, m = 0, me = 0, mi = 0, m_orig = 0;
   std::vector<int32_t> Qp, Qi, Ap, Ai, ATp, ATi;
   std::vector<int32_t> ATperm;   // ATx[k] == Ax[ATperm[k]]
+  std::vector<int32_t> Qop, Qoi;  // Q without its diagonal
+  std::vector<double> Qox, Qdiag;
   std::vector<double> Qx, Ax, ATx;
   std::vector<double> c, xl, xu, b;
   std::vector<int32_t> row_of;   // original row of each internal row
@@ -83,11 +85,15 @@ class Solver {
   double *Qraw_ = nullptr, *Araw_ = nullptr, *ATraw_ = nullptr;
   double *Qv_ = nullptr, *Av_ = nullptr, *ATv_ = nullptr;
   int32_t *atperm_ = nullptr;
+  int32_t *Qop_ = nullptr, *Qoi_ = nullptr;
+  double *Qoraw_ = nullptr, *Qov_ = nullptr, *qdiag_raw_ = nullptr, *qdiag_ = nullptr;
+  bool sample_now_ = false;
+  int64_t slot_count_ = 0;
   double bE_norm_ = 0.0, bI_norm_ = 0.0, c_norm_ = 0.0;
   double *craw_ = nullptr, *xlraw_ = nullptr, *xuraw_ = nullptr, *braw_ = nullptr;
   double *c_ = nullptr, *lo_ = nullptr, *hi_ = nullptr, *b_ = nullptr;
   double *Fx2_ = nullptr, *Fs2_ = nullptr, *Fr2_ = nullptr, *E2buf_ = nullptr;
-  Csr Q_{}, A_{}, AT_{}, Qr_{}, Ar_{}, ATr_{};
+  Csr Q_{}, A_{}, AT_{}, Qr_{}, Ar_{}, ATr_{}, Qo_{};
   Part px_{}, ps_{}, pr_{}, pq_{}, pa_{}, pt_{};
   InnerParams ip_{};
   double gamma_ = 0.0;

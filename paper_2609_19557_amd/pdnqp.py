@@ -60,6 +60,8 @@ class Settings(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("trace_iters", ctypes.c_int32),
         ("trace_trials", ctypes.c_int32),
+        ("verbose", ctypes.c_int32),
+        ("center_floor", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),

@@ -44,6 +44,7 @@ def _gpu_kwargs(st: O.Settings):
     kw = {k: getattr(st, k) for k in keys}
     kw["max_outer"] = int(min(st.max_outer, 2**62))
     kw["penalty_gate"] = int(st.penalty_gate)
+    kw["center_floor"] = int(st.center_floor)
     kw["time_limit_s"] = st.time_limit if math.isfinite(st.time_limit) else math.inf
     return kw
 
