@@ -143,6 +143,22 @@ def main():
         cpu = cpu_baseline(prob, args.cpu_iters)
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
+    # practical stream peak: a plain device copy of known size (512 MB -> 512 MB)
+    a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    roofline["copy_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(dom["GBps"] / copy_gbs, 4)
+
     value = info["inner_accepted"] / wall
     out = {
         "metric": METRIC,
