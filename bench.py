@@ -28,6 +28,19 @@ sys.path.insert(0, ROOT)
 METRIC = "inner PDHG iters/s & time-to-1e-4 KKT at n≈1M; SpMV HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 
+# Memory-side bytes per launch from the two rocprofv3 counter passes
+# (FETCH_SIZE, WRITE_SIZE) on the large FP64 workload, scaled by the same
+# counters on a plain 8 MB copy kernel; valid only for the kernel source they
+# were taken on (profiles/traffic_trial_kernels_large_fp64.md).
+PMC_TRAFFIC = {"source_sha256_prefix": "128152478a0939cd", "workload": "large", "dtype": "f64",
+               "bytes": {"qa_spmv": 749.5e6, "xtrial": 95.9e6, "at_spmv": 193.1e6}}
+
+
+def _kernel_source_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2609_19557_amd", "csrc", "pdnqp_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
 
 def _describe(prob):
     return (f"random indefinite sparse QP n={prob['n']:,} m={prob['m']:,} "
@@ -116,9 +129,13 @@ def main():
                         "avg_us": round(k["avg_us"], 3), "total_ms": round(k["total_ms"], 3),
                         "bytes_per_launch": k["bytes_per_launch"], "GBps": round(gbs, 1)})
     dom = max(kernels, key=lambda k: k["total_ms"])
+    traffic = None
+    if (_kernel_source_sha() == PMC_TRAFFIC["source_sha256_prefix"] and
+            args.workload == PMC_TRAFFIC["workload"]):
+        traffic = PMC_TRAFFIC["bytes"].get(dom["name"])
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": dom["GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom["GBps"] / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(dom["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic}
     trial_us = sum(k["avg_us"] for k in kernels)
     trial_bytes = sum(k["bytes_per_launch"] for k in kernels)
 
