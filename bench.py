@@ -38,7 +38,7 @@ PMC_TRAFFIC = {"source_sha256_prefix": "128152478a0939cd", "workload": "large", 
 
 def _kernel_source_sha():
     import hashlib
-    path = os.path.join(ROOT, "paper_2609_19557_amd", "csrc", "pdnqp_kernels.hip")
+    path = os.path.join(ROOT, "paper_2609_19557_amd", "csrc", "pdnqp_iter.hip")
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
@@ -91,6 +91,11 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--tol-time-limit", type=float, default=90.0)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32",
+                    help="fp32: FP32 matrix values and inner vectors with FP64 reductions, FP64 "
+                         "outer update and final check (the large workload's stated arithmetic)")
+    ap.add_argument("--no-other-precision", action="store_true",
+                    help="skip timing the other precision on the same instance")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -106,12 +111,15 @@ def main():
     print(f"[bench] instance: {_describe(prob)}", file=sys.stderr, flush=True)
 
     # warm-up (separate handle, same data)
-    sw = P.Solver.from_problem(prob, use_torch=True, max_outer=max(1, args.warmup))
+    sw = P.Solver.from_problem(prob, use_torch=True, max_outer=max(1, args.warmup),
+                               precision=P.FP32 if args.precision == "fp32" else P.FP64)
     sw.solve(1e-4, 1e-4)
     sw.close()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
-    s = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32)
+    prec = P.FP32 if args.precision == "fp32" else P.FP64
+    s = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32,
+                              precision=prec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x, lam, info = s.solve(1e-4, 1e-4)
@@ -131,7 +139,7 @@ def main():
     dom = max(kernels, key=lambda k: k["total_ms"])
     traffic = None
     if (_kernel_source_sha() == PMC_TRAFFIC["source_sha256_prefix"] and
-            args.workload == PMC_TRAFFIC["workload"]):
+            args.workload == PMC_TRAFFIC["workload"] and args.precision == "fp64"):
         traffic = PMC_TRAFFIC["bytes"].get(dom["name"])
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": dom["GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -142,7 +150,7 @@ def main():
     ttt = None
     if not args.no_time_to_tol:
         st = P.Solver.from_problem(prob, use_torch=True, outer_scaling=P.SCALE_RUIZ_QA,
-                                   time_limit_s=args.tol_time_limit)
+                                   time_limit_s=args.tol_time_limit, precision=prec)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, _, inf2 = st.solve(1e-4, 1e-4)
@@ -154,6 +162,25 @@ def main():
                "inner_iters_per_s": round(inf2["inner_accepted"] / max(1e-9, inf2["solve_s"]), 1)}
         st.close()
         print(f"[bench] time-to-1e-4: {ttt}", file=sys.stderr, flush=True)
+
+    other = None
+    if not args.no_other_precision:
+        oprec = P.FP64 if args.precision == "fp32" else P.FP32
+        so = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32,
+                                   precision=oprec)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, _, io = so.solve(1e-4, 1e-4)
+        torch.cuda.synchronize()
+        wo = time.perf_counter() - t2
+        other = {"precision": "fp64" if oprec == P.FP64 else "fp32 bulk, fp64 reductions",
+                 "value": round(io["inner_accepted"] / wo, 2), "unit": "inner iters/s",
+                 "steps": io["outer_iters"], "inner_accepted": io["inner_accepted"],
+                 "kernels": [{"name": k["name"], "avg_us": round(k["avg_us"], 3),
+                              "GBps": round(k["bytes_per_launch"] / (k["avg_us"] * 1e-6) / 1e9, 1)
+                              if k["avg_us"] > 0 else 0.0} for k in so.kernel_stats()]}
+        so.close()
+        print(f"[bench] other precision: {other}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -188,15 +215,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {_describe(prob)}", "seed": args.seed,
                    "outer_scaling": "ruiz_a (paper)", "step": "one outer iteration",
+                   "precision": ("fp32 bulk (matrix values, inner vectors), fp64 reductions, "
+                                 "fp64 outer update and final check" if args.precision == "fp32"
+                                 else "fp64"),
                    "inner_accepted": info["inner_accepted"], "inner_trials": info["inner_trials"],
                    "setup_s": round(info["setup_s"], 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
+        "other_precision": other,
         "trial": {"us_per_trial_kernels": round(trial_us, 3),
                   "bytes_per_trial": trial_bytes,
                   "GBps_per_trial": round(trial_bytes / (trial_us * 1e-6) / 1e9, 1)

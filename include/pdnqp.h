@@ -61,6 +61,12 @@ enum {
   PDNQP_SCALE_RUIZ_QA = 2  /* Ruiz sweeps where a column's norm also counts the symmetric Q */
 };
 
+/* Arithmetic of the inner iteration (settings.precision). */
+enum {
+  PDNQP_FP64 = 0,
+  PDNQP_FP32 = 1
+};
+
 /* Solver parameters.  Obtain defaults with pdnqp_default_settings() and
  * override fields.  Fields marked [paper] take the defaults of the paper's
  * parameter table; fields marked [reading] fix points the paper leaves
@@ -100,6 +106,9 @@ typedef struct pdnqp_settings {
   int32_t trace_trials;    /* record (L, R, accepted) of the first N trials and the first N checks */
   int32_t verbose;         /* 1: one line per outer iteration on stderr */
   int32_t center_floor;    /* [reading] centre-update tolerances never fall below eps_abs, eps_rel; 1 */
+  int32_t precision;       /* PDNQP_FP64 (default) or PDNQP_FP32: FP32 matrix values and inner
+                              vectors, FP64 reductions, FP64 outer update and final check */
+  int32_t reserved1;
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */

@@ -793,7 +793,7 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
             status = TIME_LIMIT
             break
     # unscale (Section 3.1) and map back to the caller's rows
-    x_orig = S.Dx * x
+    x_orig = np.clip(S.Dx * x, P.xl, P.xu)   # unscaling may step an ulp outside the box
     lam_scaled_int = lam
     lam_int_orig = S.Dc * lam / S.c_obj
     lam_out = np.zeros(prob["A"].shape[0])

@@ -6,4 +6,4 @@ its Python binding."""
 
 from .pdnqp import (Solver, default_settings, load, solve_batch, PdnqpError,  # noqa: F401
                     SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR, STATUS_NAMES,
-                    SCALE_RUIZ_A, SCALE_NONE, SCALE_RUIZ_QA)
+                    SCALE_RUIZ_A, SCALE_NONE, SCALE_RUIZ_QA, FP64, FP32)

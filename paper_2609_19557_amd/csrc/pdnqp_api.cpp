@@ -148,7 +148,8 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
     if (st.ruiz_sweeps < 0 || st.check_every < 1 || st.max_inner < 1 || st.max_rejects < 1 ||
         st.max_outer < 0 || st.lanczos_iters < 1 || !(st.omega0 > 0) || !(st.sigma_init > 0) ||
         !(st.delta_gamma > 0) || !(st.step_boost > 0) || st.outer_scaling < 0 ||
-        st.outer_scaling > 2 || st.trace_iters < 0 || st.trace_trials < 0)
+        st.outer_scaling > 2 || st.trace_iters < 0 || st.trace_trials < 0 ||
+        (st.precision != PDNQP_FP64 && st.precision != PDNQP_FP32))
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);

@@ -91,15 +91,35 @@ struct InnerParams {
   double restart_suff, restart_nec, restart_art;
 };
 
-struct Csr {
+template <typename T>
+struct CsrT {
   const int32_t *p;
   const int32_t *i;
-  const double *v;
+  const T *v;
   int32_t rows;
   int32_t G;           // lanes per row (power of two, 2..32) of the row-group kernels
   const int32_t *rb;   // CSR-stream row blocks: block b owns rows [rb[b], rb[b+1])
   int32_t nrb;         // number of row blocks
   int32_t pad;
+};
+using Csr = CsrT<double>;
+
+// The vectors of the inner iteration, in the bulk type T (double for the
+// FP64 path, float for the FP32-bulk path; the FP64 path aliases Vecs).
+// Reductions and traces stay FP64.
+template <typename T>
+struct IterVecs {
+  const T *lo, *hi, *b, *qdiag;
+  T *sigma, *lam, *qx;
+  T *taub_x, *taub_s, *taub_r, *etab;
+  T *S2x, *S2s, *S2r, *E2;
+  T *X[2], *QX[2], *ATY[2], *S[2], *R[2], *Y[2], *BW[2];
+  T *xbar, *qxbar, *sbar, *rbar, *ybar;
+  T *xa, *sa, *ra, *ya;
+  T *axbar, *atybar;
+  double *partial;
+  double *trace_w, *trace_y, *trace_tr;
+  int32_t *trace_ck;
 };
 
 // Row blocks for the CSR-stream kernels: consecutive rows whose nonzeros fit
@@ -142,33 +162,41 @@ struct Part {
 
 Part make_part(int32_t rows, int32_t G, int32_t max_blocks);
 
-// ---- per-trial kernels -----------------------------------------------------
-void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px);
-// Q: the off-diagonal part of Q (its diagonal is v.qdiag)
-void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &Q,
-               const Csr &A, const Part &pq, const Part &pa);
-void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &AT,
-               const Part &pt);
+// ---- inner iteration (templated on the bulk type; pdnqp_iter.hip) ----------
+int xtrial_blocks(int n);
+template <typename T>
+void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v);
+// Qoff: Q without its diagonal (the diagonal is v.qdiag)
+template <typename T>
+void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+               const CsrT<T> &Qoff, const CsrT<T> &A);
+template <typename T>
+void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+               const CsrT<T> &AT);
 // acceptance test of the trial (one workgroup), after launch_at
-void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Csr &A,
-                   const Csr &AT);
-void launch_trace(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
-                  const Part &pr);
+void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
+                   double *trace_tr, int a_nrb, int at_nrb);
+template <typename T>
+void launch_trace(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v);
+template <typename T>
+void launch_flush(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                  const Part &px, const Part &pr);
+template <typename T>
+void launch_check_spmv(hipStream_t st, Ctrl *c, const IterVecs<T> &v, const CsrT<T> &A,
+                       const CsrT<T> &AT, const Part &pa, const Part &pt);
+template <typename T>
+void launch_check(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                  const Part &px, const Part &ps, const Part &pr);
+template <typename T>
+void launch_apply(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                  const Part &px, const Part &pr);
+template <typename T>
+void launch_inner_init(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                       const CsrT<T> &Qoff, const CsrT<T> &AT, const Part &pr);
+template <typename D, typename S>
+void launch_cast(hipStream_t st, D *dst, const S *src, int64_t n);
 
-// ---- periodic check --------------------------------------------------------
-void launch_flush(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
-                  const Part &pr);
-void launch_check_spmv(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
-                       const Csr &A, const Csr &AT, const Part &pa, const Part &pt);
-void launch_check(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
-                  const Part &ps, const Part &pr);
-void launch_apply(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v, const Part &px,
-                  const Part &pr);
-
-// ---- inner QP formation ----------------------------------------------------
-void launch_inner_init(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
-                       const Csr &Q, const Csr &AT, const Part &pq, const Part &pr,
-                       double gamma);
+// ---- inner QP formation (FP64) ---------------------------------------------
 void launch_inner_ruiz_sweep(hipStream_t st, const InnerParams &p, const Vecs &v, const Csr &A,
                              const Csr &AT, const Part &pa, const Part &pt, double *Fx_new,
                              double *Fs_new, double *Fr_new, double *E_new);

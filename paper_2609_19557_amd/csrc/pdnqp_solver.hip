@@ -182,6 +182,29 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   v_.Fx = D(n); v_.Fs = D(mi); v_.Fr = D(m); v_.tmp_n = D(n); v_.tmp_m = D(m);
   Fx2_ = D(n); Fs2_ = D(mi); Fr2_ = D(m); E2buf_ = D(m);
   v_.partial = D((size_t)kMaxParts * 32);
+  fp32_ = st_.precision == PDNQP_FP32;
+  if (fp32_) {
+    auto F = [&](size_t count) -> float * {
+      float *p = (float *)dalloc(count * sizeof(float));
+      ok = ok && p;
+      return p;
+    };
+    IterVecs<float> &w = iv32_;
+    float *lo = F(n), *hi = F(n), *b = F(m), *qd = F(n);
+    w.lo = lo; w.hi = hi; w.b = b; w.qdiag = qd;
+    w.sigma = F(m); w.lam = F(m); w.qx = F(n);
+    w.taub_x = F(n); w.taub_s = F(mi); w.taub_r = F(m); w.etab = F(m);
+    w.S2x = F(n); w.S2s = F(mi); w.S2r = F(m); w.E2 = F(m);
+    for (int k = 0; k < 2; ++k) {
+      w.X[k] = F(n); w.QX[k] = F(n); w.ATY[k] = F(n);
+      w.S[k] = F(mi); w.R[k] = F(m); w.Y[k] = F(m); w.BW[k] = F(m);
+    }
+    w.xbar = F(n); w.qxbar = F(n); w.sbar = F(mi); w.rbar = F(m); w.ybar = F(m);
+    w.xa = F(n); w.sa = F(mi); w.ra = F(m); w.ya = F(m);
+    w.axbar = F(m); w.atybar = F(n);
+    Qo32v_ = F(nzo); A32v_ = F(nza); AT32v_ = F(nza);
+    w.partial = v_.partial;
+  }
   if (!ok) {
     err = "device allocation failed";
     return PDNQP_E_NOMEM;
@@ -236,6 +259,9 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   if ((r = check(hipStreamSynchronize(stream_), "row-block upload", err))) return r;
   Q_ = Csr{Qp_, Qi_, Qv_, n, GQ, qrb, nq, 0};
   Qo_ = Csr{Qop_, Qoi_, Qov_, n, pick_G(nzo, n), qorb, nqo, 0};
+  Qo32_ = CsrT<float>{Qop_, Qoi_, Qo32v_, n, Qo_.G, qorb, nqo, 0};
+  A32_ = CsrT<float>{Ap_, Ai_, A32v_, m, GA, arb, na, 0};
+  AT32_ = CsrT<float>{ATp_, ATi_, AT32v_, n, GT, atrb, nt, 0};
   v_.qdiag = qdiag_;
   A_ = Csr{Ap_, Ai_, Av_, m, GA, arb, na, 0};
   AT_ = Csr{ATp_, ATi_, ATv_, n, GT, atrb, nt, 0};
@@ -256,12 +282,13 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   timers_[TM_AT].name = "at_spmv";
   timers_[TM_DECIDE].name = "decide";
   const double me = qp_.me;
-  timers_[TM_XTRIAL].bytes = 12.0 * 8.0 * n;
+  const double vb = fp32_ ? 4.0 : 8.0;  // bytes per value of the bulk type
+  timers_[TM_XTRIAL].bytes = 12.0 * vb * n;
   // Q part: off-diagonal values+indices, row pointers, x_tr once, diagonal, Q x_tr written;
   // A part: values+indices, row pointers, x_tr once, row-local vectors
-  timers_[TM_QA].bytes = 12.0 * nzo + 4.0 * (n + 1) + 24.0 * n + 12.0 * nza + 4.0 * (m + 1) +
-                         8.0 * n + 15.0 * 8.0 * me + 20.0 * 8.0 * mi;
-  timers_[TM_AT].bytes = 12.0 * nza + 4.0 * (n + 1) + 8.0 * m + 8.0 * n + 5.0 * 8.0 * n;
+  timers_[TM_QA].bytes = (4.0 + vb) * nzo + 4.0 * (n + 1) + 3.0 * vb * n + (4.0 + vb) * nza +
+                         4.0 * (m + 1) + vb * n + 15.0 * vb * me + 20.0 * vb * mi;
+  timers_[TM_AT].bytes = (4.0 + vb) * nza + 4.0 * (n + 1) + vb * m + vb * n + 5.0 * vb * n;
   timers_[TM_DECIDE].bytes = 0.0;
   return PDNQP_OK;
 }
@@ -427,6 +454,15 @@ int Solver::setup(const double *x0c, const double *lam0_int, double &c_obj, doub
   launch_fill(stream_, v_.sigma, s0, m);
   launch_copy(stream_, v_.z, v_.X[0], n);
   launch_elem(stream_, EL_NEG, v_.Y[0], v_.lam, nullptr, 0.0, m);
+  if (fp32_) {
+    launch_cast<float, double>(stream_, Qo32v_, Qov_, (int64_t)qp_.Qoi.size());
+    launch_cast<float, double>(stream_, A32v_, Av_, (int64_t)qp_.Ai.size());
+    launch_cast<float, double>(stream_, AT32v_, ATv_, (int64_t)qp_.Ai.size());
+    launch_cast<float, double>(stream_, const_cast<float *>(iv32_.qdiag), qdiag_, n);
+    launch_cast<float, double>(stream_, const_cast<float *>(iv32_.lo), lo_, n);
+    launch_cast<float, double>(stream_, const_cast<float *>(iv32_.hi), hi_, n);
+    launch_cast<float, double>(stream_, const_cast<float *>(iv32_.b), b_, m);
+  }
   return check(hipGetLastError(), "setup kernels", err);
 }
 
@@ -449,13 +485,69 @@ void Solver::form_inner(double gamma) {
     }
   }
   launch_steps(stream_, ip_, v_, Q_, A_, AT_, 1.0 / gamma, st_.step_boost);
-  launch_inner_init(stream_, ctrl_, ip_, v_, Q_, AT_, pq_, pr_, gamma);
   InnerParams pi = ip_;
   pi.mode_init = 1;
-  launch_check(stream_, ctrl_, pi, v_, px_, ps_, pr_);
+  if (fp32_) {
+    // per-outer-step data and the warm-started state into the FP32 bulk buffers
+    const int32_t n = qp_.n, m = qp_.m, mi = qp_.mi;
+    launch_cast<float, double>(stream_, iv32_.sigma, v_.sigma, m);
+    launch_cast<float, double>(stream_, iv32_.lam, v_.lam, m);
+    launch_cast<float, double>(stream_, iv32_.qx, v_.qx, n);
+    launch_cast<float, double>(stream_, iv32_.taub_x, v_.taub_x, n);
+    launch_cast<float, double>(stream_, iv32_.taub_s, v_.taub_s, mi);
+    launch_cast<float, double>(stream_, iv32_.taub_r, v_.taub_r, m);
+    launch_cast<float, double>(stream_, iv32_.etab, v_.etab, m);
+    launch_cast<float, double>(stream_, iv32_.S2x, v_.S2x, n);
+    launch_cast<float, double>(stream_, iv32_.S2s, v_.S2s, mi);
+    launch_cast<float, double>(stream_, iv32_.S2r, v_.S2r, m);
+    launch_cast<float, double>(stream_, iv32_.E2, v_.E2, m);
+    cast_state_to32(cur);
+    launch_inner_init<float>(stream_, ctrl_, ip_, iv32_, Qo32_, AT32_, pr_);
+    launch_check<float>(stream_, ctrl_, pi, iv32_, px_, ps_, pr_);
+  } else {
+    const IterVecs<double> iv = iv64();
+    launch_inner_init<double>(stream_, ctrl_, ip_, iv, Qo_, AT_, pr_);
+    launch_check<double>(stream_, ctrl_, pi, iv, px_, ps_, pr_);
+  }
 }
 
-int Solver::run_inner(double deadline, std::string &err) {
+// The FP64 iteration vectors alias the solver's FP64 buffers.
+IterVecs<double> Solver::iv64() const {
+  IterVecs<double> iv{};
+  iv.lo = v_.lo; iv.hi = v_.hi; iv.b = v_.b; iv.qdiag = v_.qdiag;
+  iv.sigma = v_.sigma; iv.lam = v_.lam; iv.qx = v_.qx;
+  iv.taub_x = v_.taub_x; iv.taub_s = v_.taub_s; iv.taub_r = v_.taub_r; iv.etab = v_.etab;
+  iv.S2x = v_.S2x; iv.S2s = v_.S2s; iv.S2r = v_.S2r; iv.E2 = v_.E2;
+  for (int k = 0; k < 2; ++k) {
+    iv.X[k] = v_.X[k]; iv.QX[k] = v_.QX[k]; iv.ATY[k] = v_.ATY[k]; iv.S[k] = v_.S[k];
+    iv.R[k] = v_.R[k]; iv.Y[k] = v_.Y[k]; iv.BW[k] = v_.BW[k];
+  }
+  iv.xbar = v_.xbar; iv.qxbar = v_.qxbar; iv.sbar = v_.sbar; iv.rbar = v_.rbar; iv.ybar = v_.ybar;
+  iv.xa = v_.xa; iv.sa = v_.sa; iv.ra = v_.ra; iv.ya = v_.ya;
+  iv.axbar = v_.axbar; iv.atybar = v_.atybar;
+  iv.partial = v_.partial;
+  iv.trace_w = v_.trace_w; iv.trace_y = v_.trace_y; iv.trace_tr = v_.trace_tr;
+  iv.trace_ck = v_.trace_ck;
+  return iv;
+}
+
+void Solver::cast_state_to32(int cur) {
+  launch_cast<float, double>(stream_, iv32_.X[cur], v_.X[cur], qp_.n);
+  launch_cast<float, double>(stream_, iv32_.S[cur], v_.S[cur], qp_.mi);
+  launch_cast<float, double>(stream_, iv32_.R[cur], v_.R[cur], qp_.m);
+  launch_cast<float, double>(stream_, iv32_.Y[cur], v_.Y[cur], qp_.m);
+  launch_cast<float, double>(stream_, iv32_.BW[cur], v_.BW[cur], qp_.m);
+}
+
+// The outer update works on FP64 copies of the inner iterate.
+void Solver::cast_state_to64(int cur) {
+  launch_cast<double, float>(stream_, v_.X[cur], iv32_.X[cur], qp_.n);
+  launch_cast<double, float>(stream_, v_.Y[cur], iv32_.Y[cur], qp_.m);
+}
+
+template <typename T>
+int Solver::run_inner(double deadline, std::string &err, const IterVecs<T> &iv, const CsrT<T> &Qo,
+                      const CsrT<T> &A, const CsrT<T> &AT) {
   for (;;) {
     const int t = hctrl_->t, tc = hctrl_->t_call;
     int slots = st_.check_every - (t % st_.check_every);
@@ -464,16 +556,19 @@ int Solver::run_inner(double deadline, std::string &err) {
     slots = std::max(slots, 1);
     for (int s = 0; s < slots; ++s) {
       sample_now_ = st_.profile > 0 && (slot_count_++ % st_.profile) == 0;
-      timed_launch(TM_XTRIAL, [&] { launch_xtrial(stream_, ctrl_, ip_, v_, px_); });
-      timed_launch(TM_QA, [&] { launch_qa(stream_, ctrl_, ip_, v_, Qo_, A_, pq_, pa_); });
-      timed_launch(TM_AT, [&] { launch_at(stream_, ctrl_, ip_, v_, AT_, pt_); });
-      timed_launch(TM_DECIDE, [&] { launch_decide(stream_, ctrl_, ip_, v_, A_, AT_); });
-      if (trace_iters_cap_ > 0) launch_trace(stream_, ctrl_, ip_, v_, px_, pr_);
+      timed_launch(TM_XTRIAL, [&] { launch_xtrial<T>(stream_, ctrl_, ip_, iv); });
+      timed_launch(TM_QA, [&] { launch_qa<T>(stream_, ctrl_, ip_, iv, Qo, A); });
+      timed_launch(TM_AT, [&] { launch_at<T>(stream_, ctrl_, ip_, iv, AT); });
+      timed_launch(TM_DECIDE, [&] {
+        launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, A.nrb, AT.nrb);
+      });
+      if (trace_iters_cap_ > 0) launch_trace<T>(stream_, ctrl_, ip_, iv);
     }
-    launch_flush(stream_, ctrl_, ip_, v_, px_, pr_);
-    launch_check_spmv(stream_, ctrl_, ip_, v_, A_, AT_, pa_, pt_);
-    launch_check(stream_, ctrl_, ip_, v_, px_, ps_, pr_);
-    launch_apply(stream_, ctrl_, ip_, v_, px_, pr_);
+    sample_now_ = false;
+    launch_flush<T>(stream_, ctrl_, ip_, iv, px_, pr_);
+    launch_check_spmv<T>(stream_, ctrl_, iv, A, AT, pa_, pt_);
+    launch_check<T>(stream_, ctrl_, ip_, iv, px_, ps_, pr_);
+    launch_apply<T>(stream_, ctrl_, ip_, iv, px_, pr_);
     int r = check(hipGetLastError(), "inner launches", err);
     if (r) return -1000 + r;
     if ((r = read_ctrl(err))) return -1000 + r;
@@ -518,6 +613,13 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   v_.trace_y = ty_;
   v_.trace_tr = ttr_;
   v_.trace_ck = tck_;
+  // the FP32 iteration vectors share the reduction and trace buffers; they
+  // must be set before the first inner-QP formation launches a check
+  iv32_.partial = v_.partial;
+  iv32_.trace_w = tw_;
+  iv32_.trace_y = ty_;
+  iv32_.trace_tr = ttr_;
+  iv32_.trace_ck = tck_;
   ip_.trace_iters_cap = trace_iters_cap_;
   ip_.trace_trials_cap = trace_trials_cap_;
   for (auto &t : timers_) {
@@ -580,7 +682,13 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       form_inner(gamma);
       if ((r = read_ctrl(err))) return r;
     }
-    const int ist = run_inner(deadline, err);
+    int ist;
+    if (fp32_) {
+      ist = run_inner<float>(deadline, err, iv32_, Qo32_, A32_, AT32_);
+      if (ist > -1000) cast_state_to64(hctrl_->cur);
+    } else {
+      ist = run_inner<double>(deadline, err, iv64(), Qo_, A_, AT_);
+    }
     if (ist <= -1000) return ist + 1000;
     k += 1;
     if (ist == ST_NUMERR) {
@@ -683,6 +791,9 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   if ((r = check(hipStreamSynchronize(stream_), "final copy", err))) return r;
   if ((r = check(hipGetLastError(), "final kernels", err))) return r;
   for (int j = 0; j < m; ++j) ls[j] = ls[j] / c_obj;
+  // the iterate lies in the scaled box; unscaling (and FP32 storage of the
+  // scaled bounds) can leave it an ulp-level step outside the caller's box
+  for (int i = 0; i < n; ++i) xs[i] = std::min(std::max(xs[i], qp_.xl[i]), qp_.xu[i]);
   std::vector<double> lam_orig(qp_.m_orig, 0.0);
   for (int j = 0; j < m; ++j) lam_orig[qp_.row_of[j]] += qp_.sign_of[j] * ls[j];
   if (x_out) std::memcpy(x_out, xs.data(), n * 8);

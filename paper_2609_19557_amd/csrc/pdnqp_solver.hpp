@@ -60,7 +60,12 @@ class Solver {
   int check(hipError_t e, const char *what, std::string &err);
   int setup(const double *x0c, const double *lam0_int, double &c_obj, double &gamma,
             double &lam_hat, std::string &err);
-  int run_inner(double deadline, std::string &err);
+  template <typename T>
+  int run_inner(double deadline, std::string &err, const IterVecs<T> &iv, const CsrT<T> &Qo,
+                const CsrT<T> &A, const CsrT<T> &AT);
+  IterVecs<double> iv64() const;
+  void cast_state_to32(int cur);
+  void cast_state_to64(int cur);
   int read_ctrl(std::string &err);
   void form_inner(double gamma);
   void ruiz_outer();
@@ -94,6 +99,11 @@ class Solver {
   double *c_ = nullptr, *lo_ = nullptr, *hi_ = nullptr, *b_ = nullptr;
   double *Fx2_ = nullptr, *Fs2_ = nullptr, *Fr2_ = nullptr, *E2buf_ = nullptr;
   Csr Q_{}, A_{}, AT_{}, Qr_{}, Ar_{}, ATr_{}, Qo_{};
+  // FP32 bulk path
+  bool fp32_ = false;
+  IterVecs<float> iv32_{};
+  CsrT<float> Qo32_{}, A32_{}, AT32_{};
+  float *Qo32v_ = nullptr, *A32v_ = nullptr, *AT32v_ = nullptr;
   Part px_{}, ps_{}, pr_{}, pq_{}, pa_{}, pt_{};
   InnerParams ip_{};
   double gamma_ = 0.0;

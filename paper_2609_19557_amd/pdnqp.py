@@ -22,6 +22,7 @@ SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR = 1, 2, 3, 4
 STATUS_NAMES = {SOLVED: "solved", MAX_ITER: "max_iter", TIME_LIMIT: "time_limit",
                 NUMERICAL_ERROR: "numerical_error"}
 SCALE_RUIZ_A, SCALE_NONE, SCALE_RUIZ_QA = 0, 1, 2
+FP64, FP32 = 0, 1
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -62,6 +63,8 @@ class Settings(ctypes.Structure):
         ("trace_trials", ctypes.c_int32),
         ("verbose", ctypes.c_int32),
         ("center_floor", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),

@@ -1,0 +1,93 @@
+"""FP32-bulk path (FP32 matrix values and inner vectors, FP64 reductions,
+FP64 outer update and final check) against the FP64 oracle.
+
+FP32 rounding (about 6e-8 per operation) is amplified along the trajectory
+like any perturbation, so iterates are compared at 1e-4 relative over the
+first accepted iterations, and full solves are judged by the termination
+test and the FP64 KKT residuals of the returned point.  The stationary point
+an FP32 run reaches may differ from the FP64 one (the problem is nonconvex);
+the tests record the objective difference.
+"""
+
+import numpy as np
+import pytest
+
+import qpgen
+from oracle import pdnqp_oracle as O
+from tests.test_gpu_parity import EDGE, _gpu_kwargs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_19557_amd as P
+    P.load()
+    return P
+
+
+def _relmax(a, b):
+    return np.abs(a - b).max() / max(1.0, np.abs(b).max())
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fp32_tracks_fp64_oracle(P, seed):
+    prob = qpgen.workload("small", seed)
+    st = O.Settings(max_outer=3, outer_scaling=2)
+    tr = O.Trace(max_iters=40)
+    O.solve(prob, st, trace=tr)
+    s = P.Solver.from_problem(prob, precision=P.FP32, trace_iters=40, trace_trials=80,
+                              **_gpu_kwargs(st))
+    s.solve(st.eps_abs, st.eps_rel)
+    t = s.trace()
+    n = min(len(tr.w), t["w"].shape[0])
+    assert n >= 30
+    for k in range(30):
+        assert _relmax(t["w"][k], tr.w[k]) <= 1e-4, f"w at {k}"
+        assert _relmax(t["y"][k], tr.y[k]) <= 1e-4, f"y at {k}"
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fp32_small_solve(P, seed):
+    prob = qpgen.workload("small", seed)
+    st = O.Settings(outer_scaling=2, max_outer=5000, time_limit=120.0)
+    res_o = O.solve(prob, st)
+    s = P.Solver.from_problem(prob, precision=P.FP32, **_gpu_kwargs(st))
+    x, lam, info = s.solve(1e-4, 1e-4)
+    assert info["status"] == O.SOLVED
+    assert info["r_p_scaled"] <= 1e-4 + 1e-4 * info["s_p_scaled"]
+    assert info["r_d_scaled"] <= 1e-4 + 1e-4 * info["s_d_scaled"]
+    # the reported final check is the FP64 KKT test of the returned point
+    rp, rd, sp_, sd = O.external_kkt(prob, x, lam)
+    assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
+    assert info["r_d"] == pytest.approx(rd, rel=1e-6, abs=1e-12)
+    assert np.all(x >= prob["xl"]) and np.all(x <= prob["xu"])
+    print(f"seed {seed}: FP32 objective {info['objective']:.6f} vs FP64 oracle "
+          f"{res_o.objective:.6f}; |x32 - x64|_inf {np.abs(x - res_o.x).max():.2e}; "
+          f"unscaled r_p {rp:.2e} r_d {rd:.2e} (oracle {res_o.r_p:.2e}, {res_o.r_d:.2e})")
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+def test_fp32_edge_cases(P, name):
+    prob = EDGE[name]
+    st = O.Settings(max_outer=12, outer_scaling=2)
+    res_o = O.solve(prob, st)
+    s = P.Solver.from_problem(prob, precision=P.FP32, **_gpu_kwargs(st))
+    x, lam, info = s.solve(st.eps_abs, st.eps_rel)
+    assert np.all(np.isfinite(x)) and np.all(np.isfinite(lam))
+    assert info["status"] in (O.SOLVED, O.MAX_ITER)
+    assert info["status"] == res_o.status or info["status"] == O.MAX_ITER
+    assert np.abs(x - res_o.x).max() <= 1e-2 * max(1.0, np.abs(res_o.x).max())
+
+
+def test_fp32_medium_first_iterations(P):
+    prob = qpgen.workload("medium", 1)
+    st = O.Settings(max_outer=1, max_inner=64, outer_scaling=0)
+    tr = O.Trace(max_iters=20)
+    O.solve(prob, st, trace=tr)
+    s = P.Solver.from_problem(prob, precision=P.FP32, trace_iters=20, **_gpu_kwargs(st))
+    s.solve(st.eps_abs, st.eps_rel)
+    t = s.trace()
+    for k in range(20):
+        assert _relmax(t["w"][k], tr.w[k]) <= 1e-4, f"w at {k}"
+        assert _relmax(t["y"][k], tr.y[k]) <= 1e-4, f"y at {k}"
