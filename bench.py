@@ -29,17 +29,28 @@ METRIC = "inner PDHG iters/s & time-to-1e-4 KKT at n≈1M; SpMV HBM GB/s vs peak
 HBM_PEAK_GBS = 8000.0
 
 # Memory-side bytes per launch from the two rocprofv3 counter passes
-# (FETCH_SIZE, WRITE_SIZE) on the large FP64 workload, scaled by the same
-# counters on a plain 8 MB copy kernel; valid only for the kernel source they
-# were taken on (profiles/traffic_trial_kernels_large_fp64.md).
-PMC_TRAFFIC = {"source_sha256_prefix": "128152478a0939cd", "workload": "large", "dtype": "f64",
-               "bytes": {"qa_spmv": 749.5e6, "xtrial": 95.9e6, "at_spmv": 193.1e6}}
+# (FETCH_SIZE, WRITE_SIZE) on the large workload, scaled by the same counters
+# on a plain 8 MB copy kernel (profiles/traffic_trial_kernels_large.md).
+# Valid only for the device code they were taken on: the hash covers the
+# kernel helpers and the kernels of the inner iteration, not the host-side
+# launch wrappers.
+PMC_TRAFFIC = {"source_sha256_prefix": "e5cd270ae9ce3ec3", "workload": "large",
+               "bytes": {"f32": {"xtrial": 48.1e6, "qa_spmv": 219.8e6, "at_spmv": 81.2e6,
+                                 "decide": 0.1e6},
+                         "f64": {"xtrial": 96.1e6, "qa_spmv": 750.4e6, "at_spmv": 194.0e6,
+                                 "decide": 0.1e6}}}
 
 
 def _kernel_source_sha():
+    """sha256 prefix of the inner-iteration device code: the device helpers
+    header plus the kernel section (anonymous namespace) of pdnqp_iter.hip."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2609_19557_amd", "csrc", "pdnqp_iter.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    csrc = os.path.join(ROOT, "paper_2609_19557_amd", "csrc")
+    helpers = open(os.path.join(csrc, "pdnqp_device.hpp"), "rb").read()
+    it = open(os.path.join(csrc, "pdnqp_iter.hip"), "rb").read()
+    beg = it.index(b"\nnamespace {\n")
+    end = it.index(b"\n}  // namespace\n", beg)
+    return hashlib.sha256(helpers + it[beg:end]).hexdigest()[:16]
 
 
 def _describe(prob):
@@ -139,13 +150,30 @@ def main():
     dom = max(kernels, key=lambda k: k["total_ms"])
     traffic = None
     if (_kernel_source_sha() == PMC_TRAFFIC["source_sha256_prefix"] and
-            args.workload == PMC_TRAFFIC["workload"] and args.precision == "fp64"):
-        traffic = PMC_TRAFFIC["bytes"].get(dom["name"])
+            args.workload == PMC_TRAFFIC["workload"]):
+        traffic = PMC_TRAFFIC["bytes"]["f32" if args.precision == "fp32" else "f64"].get(dom["name"])
     roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": dom["GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic}
     trial_us = sum(k["avg_us"] for k in kernels)
     trial_bytes = sum(k["bytes_per_launch"] for k in kernels)
+
+    # practical stream peak, measured while the GPU is still busy from the timed
+    # solve: a plain device copy of known size (512 MB read, 512 MB written)
+    a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 8 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    roofline["copy_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(dom["GBps"] / copy_gbs, 4)
 
     ttt = None
     if not args.no_time_to_tol:
@@ -186,22 +214,6 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, args.cpu_iters)
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
-
-    # practical stream peak: a plain device copy of known size (512 MB -> 512 MB)
-    a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(10):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
-    roofline["copy_GBps"] = round(copy_gbs, 1)
-    roofline["frac_of_copy"] = round(dom["GBps"] / copy_gbs, 4)
 
     value = info["inner_accepted"] / wall
     out = {

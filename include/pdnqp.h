@@ -100,15 +100,17 @@ typedef struct pdnqp_settings {
   double gamma_override;   /* > 0: use this proximal step instead of the Lanczos rule; 0 (default) */
   double step_boost;       /* multiplies the diagonal steps at every rebuild; 1 (testing knob) */
   int32_t outer_scaling;   /* PDNQP_SCALE_*, default PDNQP_SCALE_RUIZ_A */
-  int32_t profile;         /* P > 0: time the per-trial kernels of one trial slot in every P with
-                              HIP events (pdnqp_kernel_stats); 0: off */
+  int32_t profile;         /* P > 0: time the per-trial kernels of one trial slot in every P
+                              (pdnqp_kernel_stats); 0: off */
   int32_t trace_iters;     /* record unscaled inner (w, y) after each of the first N accepted trials */
   int32_t trace_trials;    /* record (L, R, accepted) of the first N trials and the first N checks */
   int32_t verbose;         /* 1: one line per outer iteration on stderr */
   int32_t center_floor;    /* [reading] centre-update tolerances never fall below eps_abs, eps_rel; 1 */
   int32_t precision;       /* PDNQP_FP64 (default) or PDNQP_FP32: FP32 matrix values and inner
                               vectors, FP64 reductions, FP64 outer update and final check */
-  int32_t reserved1;
+  int32_t graph;           /* 1: each outer step captures its chunk of trial slots and the check
+                              in a hipGraph and replays it (same kernels, same results); 0 (default):
+                              plain stream launches */
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */
@@ -187,14 +189,61 @@ int pdnqp_solve(pdnqp_solver *s, double eps_abs, double eps_rel,
                 const double *x0, const double *lambda0,
                 double *x_out, double *lambda_out, pdnqp_info *info);
 
-/* Solves `count` independent QPs (each with its own handle, all created on
- * the same device) from zero starts, writing x_out[i], lambda_out[i] and
- * infos[i] (infos may be NULL).  Returns the first error encountered; a
- * solver outcome other than PDNQP_SOLVED is not an error. */
+/* Solves `count` independent QPs (each with its own handle) from zero
+ * starts in one persistent kernel launch.  Each workgroup runs the whole
+ * method for one instance at a time -- outer scaling, Lanczos proximal
+ * step, initial penalties, then the outer iterations of Algorithm
+ * "practical outer iteration" with their inner rAPDHG solves, and the
+ * unscaling -- and then takes the next instance (largest first) from a
+ * device queue.  The steps, readings and stopping rules are those of
+ * pdnqp_solve; each handle keeps its own settings, except that
+ * time_limit_s counts from the moment a workgroup starts the instance and
+ * an infinite limit is replaced by 3600 s.
+ *  All handles must be on the same device and share one precision
+ *  (PDNQP_E_INVALID otherwise).  The launch uses the first handle's stream.
+ *  x_out[i], lambda_out[i], infos[i]: as for pdnqp_solve (infos may be
+ *  NULL); infos[i].setup_s and solve_s are the instance's own device times
+ *  (start to end of the set-up, start to end of the solve).  Traces are
+ *  recorded per handle as in pdnqp_solve.  Returns the first error; a
+ *  solver outcome other than PDNQP_SOLVED is not an error.  Not
+ *  thread-safe: handles of one batch must not be used concurrently. */
 int pdnqp_solve_batch(int32_t count, pdnqp_solver *const *solvers,
                       double eps_abs, double eps_rel,
                       double *const *x_out, double *const *lambda_out,
                       pdnqp_info *infos);
+
+/* Report of the last pdnqp_solve_batch on this thread. */
+typedef struct pdnqp_batch_report {
+  int32_t count;
+  int32_t block;       /* threads per workgroup */
+  int32_t grid;        /* workgroups launched (resident at once) */
+  int32_t lds_bytes;   /* dynamic LDS per workgroup */
+  int32_t staged;      /* instances whose gathered vectors were staged in LDS */
+  int32_t tuned;       /* 1: block size taken from the autotuner's cache */
+  double kernel_ms;    /* the persistent kernel (HIP events on the stream) */
+  double prepare_s;    /* host: start points, descriptors, uploads */
+  double finish_s;     /* host: copies back, unscaling, external KKT checks */
+  double wall_s;       /* the whole call */
+} pdnqp_batch_report;
+
+/* Copies the report; done_ms (optional, up to `cap` entries, instance order
+ * of the call) receives each instance's finish time in milliseconds after
+ * the first instance started (device clock). */
+int pdnqp_batch_last_report(pdnqp_batch_report *rep, double *done_ms, int32_t cap);
+
+/* Workgroup size for later batched solves in this process: 256, 512 or
+ * 1024; 0 returns to the autotuned choice (256 when none is cached). */
+int pdnqp_batch_set_block(int32_t block);
+
+/* Autotuner of the batched solve: runs the batch once per workgroup size
+ * with a short budget per instance (one outer step of at most
+ * `probe_inner` accepted inner iterations), keeps the fastest size for the
+ * batch's class (precision, count and mean nonzeros per instance, each
+ * rounded down to a power of two) in a process-wide cache that
+ * pdnqp_solve_batch consults, and returns it in *block_out.  ms_out
+ * (optional, 3 entries) receives the kernel time of 256, 512 and 1024. */
+int pdnqp_batch_autotune(int32_t count, pdnqp_solver *const *solvers, int32_t probe_inner,
+                         int32_t *block_out, double *ms_out);
 
 /* Releases the handle and its device memory.  NULL is a no-op. */
 void pdnqp_destroy(pdnqp_solver *s);
@@ -226,9 +275,11 @@ int pdnqp_dims(const pdnqp_solver *s, int32_t *m_e, int32_t *m_i, int32_t *d_w);
 int pdnqp_get_trace(const pdnqp_solver *s, int32_t *iters, double *w, double *y,
                     int32_t *trials, double *tr, int32_t *checks, int32_t *ck);
 
-/* Per-kernel timings gathered when settings.profile = 1 during the last
+/* Per-kernel timings gathered when settings.profile > 0 during the last
  * pdnqp_solve: for each kernel class, the launch count, summed and average
- * duration (HIP events on the solver's stream) and the kernel's algorithmic
+ * duration (HIP events that the sampled dispatches themselves stamp on the
+ * solver's stream: the kernel's execution interval, without launch gaps)
+ * and the kernel's algorithmic
  * bytes per launch (matrix values and indices once, every vector it reads
  * or writes once).  Writes up to `cap` entries; *count receives the number
  * available. */

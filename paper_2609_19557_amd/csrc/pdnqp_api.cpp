@@ -149,7 +149,8 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         st.max_outer < 0 || st.lanczos_iters < 1 || !(st.omega0 > 0) || !(st.sigma_init > 0) ||
         !(st.delta_gamma > 0) || !(st.step_boost > 0) || st.outer_scaling < 0 ||
         st.outer_scaling > 2 || st.trace_iters < 0 || st.trace_trials < 0 ||
-        (st.precision != PDNQP_FP64 && st.precision != PDNQP_FP32))
+        (st.precision != PDNQP_FP64 && st.precision != PDNQP_FP32) ||
+        (st.graph != 0 && st.graph != 1))
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);
@@ -276,17 +277,75 @@ int pdnqp_solve(pdnqp_solver *s, double eps_abs, double eps_rel, const double *x
   }
 }
 
+namespace {
+thread_local pdnqp_batch_report g_batch_report{};
+thread_local std::vector<double> g_batch_done;
+
+int batch_request(int32_t count, pdnqp_solver *const *solvers, pdnqp::BatchRequest &req) {
+  if (count < 0) return fail(PDNQP_E_INVALID, "count must be >= 0");
+  if (count > 0 && !solvers) return fail(PDNQP_E_INVALID, "NULL array argument");
+  req.solvers.resize(count);
+  for (int32_t k = 0; k < count; ++k) {
+    if (!solvers[k]) return fail(PDNQP_E_INVALID, "solver " + std::to_string(k) + " is NULL");
+    for (int32_t j = 0; j < k; ++j)
+      if (solvers[j] == solvers[k])
+        return fail(PDNQP_E_INVALID, "the same handle appears twice in the batch");
+    req.solvers[k] = &solvers[k]->s;
+  }
+  return PDNQP_OK;
+}
+}  // namespace
+
 int pdnqp_solve_batch(int32_t count, pdnqp_solver *const *solvers, double eps_abs, double eps_rel,
                       double *const *x_out, double *const *lambda_out, pdnqp_info *infos) {
   g_err.clear();
-  if (count < 0) return fail(PDNQP_E_INVALID, "count must be >= 0");
-  if (count > 0 && (!solvers || !x_out || !lambda_out))
-    return fail(PDNQP_E_INVALID, "NULL array argument");
-  for (int32_t k = 0; k < count; ++k) {
-    const int r = pdnqp_solve(solvers[k], eps_abs, eps_rel, nullptr, nullptr, x_out[k],
-                              lambda_out[k], infos ? &infos[k] : nullptr);
-    if (r != PDNQP_OK) return r;
-  }
+  if (!(eps_abs >= 0) || !(eps_rel >= 0) || eps_abs + eps_rel <= 0)
+    return fail(PDNQP_E_INVALID, "tolerances must be >= 0 and not both 0");
+  if (count > 0 && (!x_out || !lambda_out)) return fail(PDNQP_E_INVALID, "NULL array argument");
+  pdnqp::BatchRequest req;
+  int r = batch_request(count, solvers, req);
+  if (r) return r;
+  for (int32_t k = 0; k < count; ++k)
+    if (!x_out[k] || (!lambda_out[k] && solvers[k]->s.qp().m_orig > 0))
+      return fail(PDNQP_E_INVALID, "NULL output buffer for instance " + std::to_string(k));
+  req.eps_abs = eps_abs;
+  req.eps_rel = eps_rel;
+  req.x_out = x_out;
+  req.lam_out = lambda_out;
+  req.infos = infos;
+  std::string err;
+  r = pdnqp::run_batch(req, &g_batch_report, &g_batch_done, err);
+  if (r) return fail(r, err);
+  return PDNQP_OK;
+}
+
+int pdnqp_batch_last_report(pdnqp_batch_report *rep, double *done_ms, int32_t cap) {
+  if (rep) *rep = g_batch_report;
+  if (done_ms)
+    for (int32_t i = 0; i < cap && i < (int32_t)g_batch_done.size(); ++i) done_ms[i] = g_batch_done[i];
+  return PDNQP_OK;
+}
+
+int pdnqp_batch_set_block(int32_t block) {
+  g_err.clear();
+  if (block != 0 && block != 256 && block != 512 && block != 1024)
+    return fail(PDNQP_E_INVALID, "block must be 0, 256, 512 or 1024");
+  pdnqp::set_batch_block(block);
+  return PDNQP_OK;
+}
+
+int pdnqp_batch_autotune(int32_t count, pdnqp_solver *const *solvers, int32_t probe_inner,
+                         int32_t *block_out, double *ms_out) {
+  g_err.clear();
+  if (count < 1) return fail(PDNQP_E_INVALID, "count must be >= 1");
+  if (probe_inner < 1) return fail(PDNQP_E_INVALID, "probe_inner must be >= 1");
+  pdnqp::BatchRequest req;
+  int r = batch_request(count, solvers, req);
+  if (r) return r;
+  req.probe_inner = probe_inner;
+  std::string err;
+  r = pdnqp::autotune_batch(req, block_out, ms_out, err);
+  if (r) return fail(r, err);
   return PDNQP_OK;
 }
 

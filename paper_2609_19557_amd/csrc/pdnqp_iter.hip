@@ -9,6 +9,8 @@
 // nothing when its phase is not due, so the host can enqueue fixed chunks.
 #include "pdnqp_device.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -200,55 +202,74 @@ __global__ __launch_bounds__(kBlock) void k_at_stream(Ctrl *__restrict__ c, Inne
   block_reduce<2>(vals, 0u, v.partial + PS_AT * kMaxParts, blockIdx.x);
 }
 
+// Control-block fields the acceptance decision reads, loaded at the start of
+// the decision kernel so that their latency overlaps the partial loads.
+struct DecideIn {
+  int cur, N, t, t_call, rejects, ntr;
+  double sc, om;
+  int64_t trials, accepted, rejected;
+};
+
+__device__ __forceinline__ DecideIn load_decide_in(const Ctrl *__restrict__ c) {
+  DecideIn d;
+  d.cur = c->cur;
+  d.N = c->N;
+  d.t = c->t;
+  d.t_call = c->t_call;
+  d.rejects = c->rejects;
+  d.ntr = c->trace_trials_n;
+  d.sc = c->step_scale;
+  d.om = c->omega;
+  d.trials = c->trials;
+  d.accepted = c->accepted;
+  d.rejected = c->rejected;
+  return d;
+}
+
 // Decision of the acceptance test (adaptive-condition) from the three
-// kernels' sums; run by one thread.  All control-block fields are loaded
-// first (one batch of independent loads) and written back at the end.
-__device__ void accept_decision(Ctrl *__restrict__ c, const InnerParams &p, double *trace_tr,
-                                double sx, const double (&sr)[4], double sum_hdx,
-                                double sum_bdy) {
-  const int cur = c->cur;
-  const int N = c->N, t = c->t, t_call = c->t_call, rejects = c->rejects;
-  const int ntr = c->trace_trials_n;
-  const double sc = c->step_scale;
-  const double om = c->omega;
-  const int64_t trials = c->trials, accepted = c->accepted, rejected = c->rejected;
+// kernels' sums; run by one thread.
+__device__ void accept_decision(Ctrl *__restrict__ c, const DecideIn &d, const InnerParams &p,
+                                double *trace_tr, double sx, const double (&sr)[4],
+                                double sum_hdx, double sum_bdy) {
+  const double sc = d.sc;
+  const double om = d.om;
   const double L = 0.5 * ((om / sc) * (sx + sr[0]) + sr[1] / (sc * om));
   const double R = 0.5 * (sum_hdx + sr[2]) + (sum_bdy + sr[3]);
   c->sum_x = sx;
   for (int k = 0; k < 4; ++k) c->sum_row[k] = sr[k];
   c->L = L;
   c->R = R;
-  c->trials = trials + 1;
+  c->trials = d.trials + 1;
   const bool finite = isfinite(L) && isfinite(R);
   const bool acc = finite && (L >= R);
-  if (ntr < p.trace_trials_cap) {
-    trace_tr[3 * ntr + 0] = L;
-    trace_tr[3 * ntr + 1] = R;
-    trace_tr[3 * ntr + 2] = acc ? 1.0 : 0.0;
-    c->trace_trials_n = ntr + 1;
+  if (d.ntr < p.trace_trials_cap) {
+    trace_tr[3 * d.ntr + 0] = L;
+    trace_tr[3 * d.ntr + 1] = R;
+    trace_tr[3 * d.ntr + 2] = acc ? 1.0 : 0.0;
+    c->trace_trials_n = d.ntr + 1;
   }
   c->last_acc = acc ? 1 : 0;
   if (!finite) {
     c->state = ST_NUMERR;
     c->pending = 0;
   } else if (acc) {
-    c->alpha_pend = 2.0 / ((double)N + 2.0);
+    c->alpha_pend = 2.0 / ((double)d.N + 2.0);
     c->pending = 1;
-    c->cur = cur ^ 1;
-    c->N = N + 1;
-    c->t = t + 1;
-    c->t_call = t_call + 1;
+    c->cur = d.cur ^ 1;
+    c->N = d.N + 1;
+    c->t = d.t + 1;
+    c->t_call = d.t_call + 1;
     c->rejects = 0;
-    c->accepted = accepted + 1;
-    if (((t + 1) % p.check_every) == 0 || t_call + 1 >= p.max_inner) c->state = ST_CHECK_DUE;
+    c->accepted = d.accepted + 1;
+    if (((d.t + 1) % p.check_every) == 0 || d.t_call + 1 >= p.max_inner) c->state = ST_CHECK_DUE;
   } else {
     double kappa = p.shrink_safety * L / R;
     kappa = kappa < p.shrink_min ? p.shrink_min : (kappa > p.shrink_max ? p.shrink_max : kappa);
     c->step_scale = kappa * sc;
     c->pending = 0;
-    c->rejects = rejects + 1;
-    c->rejected = rejected + 1;
-    if (rejects + 1 >= p.max_rejects) c->state = ST_NUMERR;
+    c->rejects = d.rejects + 1;
+    c->rejected = d.rejected + 1;
+    if (d.rejects + 1 >= p.max_rejects) c->state = ST_NUMERR;
   }
 }
 
@@ -260,6 +281,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide(Ctrl *__restrict__ c,
                                                            double *trace_tr, int gx, int ga,
                                                            int gt) {
   const int state = c->state;
+  const DecideIn din = load_decide_in(c);
   double a[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) a[k] = 0.0;
@@ -302,7 +324,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide(Ctrl *__restrict__ c,
       r[k] = acc;
     }
     const double sr[4] = {r[1], r[2], r[3], r[4]};
-    accept_decision(c, p, trace_tr, r[0], sr, r[5], r[6]);
+    accept_decision(c, din, p, trace_tr, r[0], sr, r[5], r[6]);
   }
 }
 
@@ -727,34 +749,44 @@ int xtrial_blocks(int n) {
 // ===========================================================================
 // Launch wrappers.
 // ===========================================================================
+// Plain launch, or a launch whose dispatch records `ev` when timing is asked for.
+template <typename... KArgs, typename... Args>
+void launch_ev(void (*k)(KArgs...), dim3 grid, dim3 block, hipStream_t st, LaunchEvents ev,
+               Args... args) {
+  if (ev.start) {
+    hipExtLaunchKernelGGL(k, grid, block, 0, st, ev.start, ev.stop, 0, static_cast<KArgs>(args)...);
+  } else {
+    hipLaunchKernelGGL(k, grid, block, 0, st, static_cast<KArgs>(args)...);
+  }
+}
+
 template <typename T>
-void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v) {
-  hipLaunchKernelGGL(k_xtrial<T>, dim3(xtrial_blocks(p.n)), dim3(kBlock), 0, st, c, p, v);
+void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                   LaunchEvents ev) {
+  launch_ev(k_xtrial<T>, dim3(xtrial_blocks(p.n)), dim3(kBlock), st, ev, c, p, v);
 }
 
 template <typename T>
 void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
-               const CsrT<T> &Q, const CsrT<T> &A) {
+               const CsrT<T> &Q, const CsrT<T> &A, LaunchEvents ev) {
   const int gq = std::min(Q.nrb, kMaxParts);
   const int ga = std::min(A.nrb, kMaxParts);
-  hipLaunchKernelGGL(k_qa_stream<T>, dim3(nz(gq + ga)), dim3(kBlock), 0, st, c, p, v, Q, A, gq,
-                     ga);
+  launch_ev(k_qa_stream<T>, dim3(nz(gq + ga)), dim3(kBlock), st, ev, c, p, v, Q, A, gq, ga);
 }
 
 template <typename T>
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
-               const CsrT<T> &AT) {
+               const CsrT<T> &AT, LaunchEvents ev) {
   const int g = std::min(AT.nrb, kMaxParts);
-  hipLaunchKernelGGL(k_at_stream<T>, dim3(nz(g)), dim3(kBlock), 0, st, c, p, v, AT);
+  launch_ev(k_at_stream<T>, dim3(nz(g)), dim3(kBlock), st, ev, c, p, v, AT);
 }
 
 void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
-                   double *trace_tr, int a_nrb, int at_nrb) {
+                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev) {
   const int gx = xtrial_blocks(p.n);
   const int ga = std::min(a_nrb, kMaxParts);
   const int gt = nz(std::min(at_nrb, kMaxParts));
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideThreads), 0, st, c, p, partial, trace_tr, gx,
-                     ga, gt);
+  launch_ev(k_decide, dim3(1), dim3(kDecideThreads), st, ev, c, p, partial, trace_tr, gx, ga, gt);
 }
 
 template <typename T>
@@ -820,11 +852,12 @@ void launch_cast(hipStream_t st, D *dst, const S *src, int64_t n) {
 }
 
 #define PDNQP_INSTANTIATE(T)                                                                      \
-  template void launch_xtrial<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &); \
+  template void launch_xtrial<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,  \
+                                 LaunchEvents);                                                  \
   template void launch_qa<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,      \
-                             const CsrT<T> &, const CsrT<T> &);                                  \
+                             const CsrT<T> &, const CsrT<T> &, LaunchEvents);                    \
   template void launch_at<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,      \
-                             const CsrT<T> &);                                                   \
+                             const CsrT<T> &, LaunchEvents);                                     \
   template void launch_trace<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &);  \
   template void launch_flush<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,   \
                                 const Part &, const Part &);                                     \

@@ -449,7 +449,7 @@ Part make_part(int32_t rows, int32_t G, int32_t max_blocks) {
 static inline int nz(int b) { return b > 0 ? b : 1; }
 
 void stream_row_blocks(const int32_t *rp, int32_t rows, int32_t max_rows, int32_t *out_nrb,
-                       int32_t *rb) {
+                       int32_t *rb, int32_t tile) {
   int32_t nb = 0;
   rb[0] = 0;
   int32_t r = 0;
@@ -457,7 +457,7 @@ void stream_row_blocks(const int32_t *rp, int32_t rows, int32_t max_rows, int32_
     const int32_t start = r;
     const int32_t base = rp[r];
     ++r;
-    while (r < rows && rp[r + 1] - base <= kTile && r - start < max_rows) ++r;
+    while (r < rows && rp[r + 1] - base <= tile && r - start < max_rows) ++r;
     rb[++nb] = r;
   }
   *out_nrb = nb;

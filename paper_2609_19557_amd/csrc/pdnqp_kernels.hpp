@@ -126,7 +126,7 @@ struct IterVecs {
 // in one tile of kTile entries (a longer row gets a block of its own), at
 // most max_rows rows per block.
 void stream_row_blocks(const int32_t *rp, int32_t rows, int32_t max_rows, int32_t *out_nrb,
-                       int32_t *rb /* capacity rows + 1 */);
+                       int32_t *rb /* capacity rows + 1 */, int32_t tile = kTile);
 
 // Every device vector the kernels touch, passed by value.
 struct Vecs {
@@ -163,19 +163,26 @@ struct Part {
 Part make_part(int32_t rows, int32_t G, int32_t max_blocks);
 
 // ---- inner iteration (templated on the bulk type; pdnqp_iter.hip) ----------
+// Optional timing events of one launch: when set, the dispatch itself stamps
+// its start and end into them (the same interval a kernel tracer reports).
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
 int xtrial_blocks(int n);
 template <typename T>
-void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v);
+void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                   LaunchEvents ev = {});
 // Qoff: Q without its diagonal (the diagonal is v.qdiag)
 template <typename T>
 void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
-               const CsrT<T> &Qoff, const CsrT<T> &A);
+               const CsrT<T> &Qoff, const CsrT<T> &A, LaunchEvents ev = {});
 template <typename T>
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
-               const CsrT<T> &AT);
+               const CsrT<T> &AT, LaunchEvents ev = {});
 // acceptance test of the trial (one workgroup), after launch_at
 void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
-                   double *trace_tr, int a_nrb, int at_nrb);
+                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev = {});
 template <typename T>
 void launch_trace(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v);
 template <typename T>

@@ -79,6 +79,8 @@ enum TimerId { TM_XTRIAL = 0, TM_QA = 1, TM_AT = 2, TM_DECIDE = 3, TM_COUNT = 4 
 
 Solver::~Solver() {
   if (stream_) hipStreamSynchronize(stream_);
+  if (gexec_) hipGraphExecDestroy(gexec_);
+  if (cap_stream_) hipStreamDestroy(cap_stream_);
   for (auto &t : timers_)
     for (auto e : t.ev) hipEventDestroy(e);
   for (void *p : allocs_) dfree(p);
@@ -114,6 +116,7 @@ int Solver::check(hipError_t e, const char *what, std::string &err) {
 int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   qp_ = std::move(qp);
   st_ = st;
+  hipGetDevice(&device_);
   const int32_t n = qp_.n, m = qp_.m, mi = qp_.mi;
   const int64_t nzq = qp_.Qi.size(), nza = qp_.Ai.size();
   if (st_.hip_stream) {
@@ -293,9 +296,9 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   return PDNQP_OK;
 }
 
-void Solver::timed_launch(int which, const std::function<void()> &f) {
+void Solver::timed_launch(int which, const std::function<void(LaunchEvents)> &f) {
   if (!sample_now_) {
-    f();
+    f(LaunchEvents{});
     return;
   }
   KernelTimer &t = timers_[which];
@@ -306,9 +309,7 @@ void Solver::timed_launch(int which, const std::function<void()> &f) {
     t.ev.push_back(a);
     t.ev.push_back(b);
   }
-  hipEventRecord(t.ev[2 * t.used], stream_);
-  f();
-  hipEventRecord(t.ev[2 * t.used + 1], stream_);
+  f(LaunchEvents{t.ev[2 * t.used], t.ev[2 * t.used + 1]});
   t.used += 1;
 }
 
@@ -545,30 +546,84 @@ void Solver::cast_state_to64(int cur) {
   launch_cast<double, float>(stream_, v_.Y[cur], iv32_.Y[cur], qp_.m);
 }
 
+// One chunk of trial slots followed by the check kernels.  Slots after a
+// due check (or after the inner limit) find the state not running and exit
+// at once, so the full chunk can always be enqueued.
+template <typename T>
+void Solver::enqueue_chunk(int slots, bool sampled, const IterVecs<T> &iv, const CsrT<T> &Qo,
+                           const CsrT<T> &A, const CsrT<T> &AT) {
+  for (int s = 0; s < slots; ++s) {
+    sample_now_ = sampled && st_.profile > 0 && (slot_count_++ % st_.profile) == 0;
+    timed_launch(TM_XTRIAL, [&](LaunchEvents e) { launch_xtrial<T>(stream_, ctrl_, ip_, iv, e); });
+    timed_launch(TM_QA, [&](LaunchEvents e) { launch_qa<T>(stream_, ctrl_, ip_, iv, Qo, A, e); });
+    timed_launch(TM_AT, [&](LaunchEvents e) { launch_at<T>(stream_, ctrl_, ip_, iv, AT, e); });
+    timed_launch(TM_DECIDE, [&](LaunchEvents e) {
+      launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, A.nrb, AT.nrb, e);
+    });
+    if (trace_iters_cap_ > 0) launch_trace<T>(stream_, ctrl_, ip_, iv);
+  }
+  sample_now_ = false;
+  launch_flush<T>(stream_, ctrl_, ip_, iv, px_, pr_);
+  launch_check_spmv<T>(stream_, ctrl_, iv, A, AT, pa_, pt_);
+  launch_check<T>(stream_, ctrl_, ip_, iv, px_, ps_, pr_);
+  launch_apply<T>(stream_, ctrl_, ip_, iv, px_, pr_);
+}
+
+// Captures a full chunk (check_every slots and the check) with the current
+// inner parameters.
+template <typename T>
+int Solver::capture_chunk(std::string &err, const IterVecs<T> &iv, const CsrT<T> &Qo,
+                          const CsrT<T> &A, const CsrT<T> &AT) {
+  // captured on a private stream (the solver's stream may be the legacy
+  // default stream, which cannot be captured) and replayed on the solver's
+  if (!cap_stream_) {
+    const int rc = check(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking),
+                         "hipStreamCreate", err);
+    if (rc) return rc;
+  }
+  hipGraph_t g = nullptr;
+  hipStream_t launch_stream = stream_;
+  int r = check(hipStreamBeginCapture(cap_stream_, hipStreamCaptureModeThreadLocal),
+                "graph capture", err);
+  if (r) return r;
+  stream_ = cap_stream_;
+  enqueue_chunk<T>(st_.check_every, false, iv, Qo, A, AT);
+  stream_ = launch_stream;
+  r = check(hipStreamEndCapture(cap_stream_, &g), "graph capture", err);
+  if (r) return r;
+  if (gexec_) {
+    hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+  }
+  r = check(hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0), "graph instantiate", err);
+  hipGraphDestroy(g);
+  if (r) return r;
+  graph_valid_ = true;
+  return PDNQP_OK;
+}
+
 template <typename T>
 int Solver::run_inner(double deadline, std::string &err, const IterVecs<T> &iv, const CsrT<T> &Qo,
                       const CsrT<T> &A, const CsrT<T> &AT) {
   for (;;) {
     const int t = hctrl_->t, tc = hctrl_->t_call;
     int slots = st_.check_every - (t % st_.check_every);
-    sample_now_ = false;
     slots = std::min(slots, st_.max_inner - tc);
     slots = std::max(slots, 1);
-    for (int s = 0; s < slots; ++s) {
-      sample_now_ = st_.profile > 0 && (slot_count_++ % st_.profile) == 0;
-      timed_launch(TM_XTRIAL, [&] { launch_xtrial<T>(stream_, ctrl_, ip_, iv); });
-      timed_launch(TM_QA, [&] { launch_qa<T>(stream_, ctrl_, ip_, iv, Qo, A); });
-      timed_launch(TM_AT, [&] { launch_at<T>(stream_, ctrl_, ip_, iv, AT); });
-      timed_launch(TM_DECIDE, [&] {
-        launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, A.nrb, AT.nrb);
-      });
-      if (trace_iters_cap_ > 0) launch_trace<T>(stream_, ctrl_, ip_, iv);
+    // with profiling on, one chunk in `profile` is launched directly so that
+    // its slots can be sampled
+    const bool sampled = st_.profile > 0 && (!st_.graph || (chunk_count_ % st_.profile) == 0);
+    ++chunk_count_;
+    if (st_.graph && !sampled) {
+      if (!graph_valid_) {
+        const int rc = capture_chunk<T>(err, iv, Qo, A, AT);
+        if (rc) return -1000 + rc;
+      }
+      const int rc = check(hipGraphLaunch(gexec_, stream_), "graph launch", err);
+      if (rc) return -1000 + rc;
+    } else {
+      enqueue_chunk<T>(slots, sampled, iv, Qo, A, AT);
     }
-    sample_now_ = false;
-    launch_flush<T>(stream_, ctrl_, ip_, iv, px_, pr_);
-    launch_check_spmv<T>(stream_, ctrl_, iv, A, AT, pa_, pt_);
-    launch_check<T>(stream_, ctrl_, ip_, iv, px_, ps_, pr_);
-    launch_apply<T>(stream_, ctrl_, ip_, iv, px_, pr_);
     int r = check(hipGetLastError(), "inner launches", err);
     if (r) return -1000 + r;
     if ((r = read_ctrl(err))) return -1000 + r;
@@ -581,14 +636,12 @@ int Solver::run_inner(double deadline, std::string &err, const IterVecs<T> &iv, 
   }
 }
 
-int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double *lam0,
-                  double *x_out, double *lam_out, pdnqp_info *info, std::string &err) {
-  const double t_start = now_s();
-  const double deadline =
-      std::isfinite(st_.time_limit_s) ? t_start + st_.time_limit_s : std::numeric_limits<double>::infinity();
-  const int32_t n = qp_.n, m = qp_.m, me = qp_.me, mi = qp_.mi;
-  const int dw = n + mi + m;
-  int r;
+// Start shared by both paths: trace buffers, x0 clipped into the box,
+// lambda0 mapped to the internal rows (inequality rows kept <= 0).
+int Solver::begin(const double *x0, const double *lam0, std::vector<double> &x0c,
+                  std::vector<double> &lam0i, std::string &err) {
+  const int32_t n = qp_.n, m = qp_.m, me = qp_.me;
+  const int dw = n + qp_.mi + m;
   // trace buffers
   traced_ = false;
   trace_iters_cap_ = std::max(0, st_.trace_iters);
@@ -627,8 +680,8 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     t.total_ms = 0.0;
     t.used = 0;
   }
-  // host-side start: x0 clipped into the box, lambda0 in internal rows
-  std::vector<double> x0c(n, 0.0), lam0i(m, 0.0);
+  x0c.assign(n, 0.0);
+  lam0i.assign(m, 0.0);
   for (int i = 0; i < n; ++i) {
     double x = x0 ? x0[i] : 0.0;
     x0c[i] = x < qp_.xl[i] ? qp_.xl[i] : (x > qp_.xu[i] ? qp_.xu[i] : x);
@@ -640,6 +693,19 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       lam0i[j] = l;
     }
   }
+  return PDNQP_OK;
+}
+
+int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double *lam0,
+                  double *x_out, double *lam_out, pdnqp_info *info, std::string &err) {
+  const double t_start = now_s();
+  const double deadline =
+      std::isfinite(st_.time_limit_s) ? t_start + st_.time_limit_s : std::numeric_limits<double>::infinity();
+  const int32_t n = qp_.n, m = qp_.m, me = qp_.me, mi = qp_.mi;
+  const int dw = n + mi + m;
+  int r;
+  std::vector<double> x0c, lam0i;
+  if ((r = begin(x0, lam0, x0c, lam0i, err))) return r;
   // control block
   Ctrl hc;
   std::memset(&hc, 0, sizeof(hc));
@@ -680,6 +746,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     ip_.delta_r = delta_r;
     if (need_form) {
       form_inner(gamma);
+      graph_valid_ = false;  // the inner parameters of the chunk changed
       if ((r = read_ctrl(err))) return r;
     }
     int ist;
@@ -763,17 +830,49 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       break;
     }
   }
-  // unscale: x = Dx x_bar, lambda = Dc lambda_bar / c_obj, then caller's rows
+  // unscale: x = Dx x_bar, lambda = Dc lambda_bar (divided by c_obj in finish)
   const int cur = hctrl_->cur;
   launch_elem(stream_, EL_MUL, v_.tmp_n, v_.Dx, v_.X[cur], 0.0, n);
   launch_elem(stream_, EL_MUL, v_.tmp_m, v_.Dc, v_.lam, 0.0, m);
+  Outcome oc;
+  oc.status = status;
+  oc.outer_iters = k;
+  oc.trials = hctrl_->trials;
+  oc.accepted = hctrl_->accepted;
+  oc.rejected = hctrl_->rejected;
+  oc.restarts = hctrl_->restarts;
+  oc.checks = hctrl_->checks;
+  oc.rp = rp;
+  oc.rd = rd;
+  oc.sp = sp;
+  oc.sd = sd;
+  oc.gamma = gamma;
+  oc.lam_hat = lam_hat;
+  oc.omega = hctrl_->omega;
+  oc.c_obj = c_obj;
+  oc.setup_s = t_setup;
+  oc.trace_iters = hctrl_->trace_iters_n;
+  oc.trace_trials = hctrl_->trace_trials_n;
+  oc.trace_checks = hctrl_->trace_checks_n;
+  if ((r = finish(oc, x_out, lam_out, info, err))) return r;
+  if (info) info->solve_s = now_s() - t_start;
+  return PDNQP_OK;
+}
+
+// Copies the unscaled result (x in tmp_n, Dc lambda in tmp_m) and the trace
+// back, maps lambda to the caller's rows and fills the info record.
+int Solver::finish(const Outcome &oc, double *x_out, double *lam_out, pdnqp_info *info,
+                   std::string &err) {
+  const int32_t n = qp_.n, m = qp_.m;
+  const int dw = n + qp_.mi + m;
+  int r;
   std::vector<double> xs(n), ls(m);
   hipMemcpyAsync(xs.data(), v_.tmp_n, n * 8, hipMemcpyDeviceToHost, stream_);
   if (m) hipMemcpyAsync(ls.data(), v_.tmp_m, m * 8, hipMemcpyDeviceToHost, stream_);
   if (trace_iters_cap_ > 0 || trace_trials_cap_ > 0) {
-    got_iters_ = hctrl_->trace_iters_n;
-    got_trials_ = hctrl_->trace_trials_n;
-    got_checks_ = hctrl_->trace_checks_n;
+    got_iters_ = oc.trace_iters;
+    got_trials_ = oc.trace_trials;
+    got_checks_ = oc.trace_checks;
     h_tw_.assign((size_t)got_iters_ * dw, 0.0);
     h_ty_.assign((size_t)got_iters_ * m, 0.0);
     h_ttr_.assign((size_t)got_trials_ * 3, 0.0);
@@ -790,7 +889,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   }
   if ((r = check(hipStreamSynchronize(stream_), "final copy", err))) return r;
   if ((r = check(hipGetLastError(), "final kernels", err))) return r;
-  for (int j = 0; j < m; ++j) ls[j] = ls[j] / c_obj;
+  for (int j = 0; j < m; ++j) ls[j] = ls[j] / oc.c_obj;
   // the iterate lies in the scaled box; unscaling (and FP32 storage of the
   // scaled bounds) can leave it an ulp-level step outside the caller's box
   for (int i = 0; i < n; ++i) xs[i] = std::min(std::max(xs[i], qp_.xl[i]), qp_.xu[i]);
@@ -800,23 +899,22 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   if (lam_out && qp_.m_orig) std::memcpy(lam_out, lam_orig.data(), qp_.m_orig * 8);
   if (info) {
     std::memset(info, 0, sizeof(*info));
-    info->status = status;
-    info->outer_iters = k;
-    info->inner_trials = hctrl_->trials;
-    info->inner_accepted = hctrl_->accepted;
-    info->inner_rejected = hctrl_->rejected;
-    info->restarts = hctrl_->restarts;
-    info->checks = hctrl_->checks;
-    info->r_p_scaled = rp;
-    info->r_d_scaled = rd;
-    info->s_p_scaled = sp;
-    info->s_d_scaled = sd;
-    info->gamma = gamma;
-    info->lambda_hat = lam_hat;
-    info->omega = hctrl_->omega;
-    info->setup_s = t_setup;
+    info->status = oc.status;
+    info->outer_iters = oc.outer_iters;
+    info->inner_trials = oc.trials;
+    info->inner_accepted = oc.accepted;
+    info->inner_rejected = oc.rejected;
+    info->restarts = oc.restarts;
+    info->checks = oc.checks;
+    info->r_p_scaled = oc.rp;
+    info->r_d_scaled = oc.rd;
+    info->s_p_scaled = oc.sp;
+    info->s_d_scaled = oc.sd;
+    info->gamma = oc.gamma;
+    info->lambda_hat = oc.lam_hat;
+    info->omega = oc.omega;
+    info->setup_s = oc.setup_s;
     external_check(xs, lam_orig, info);
-    info->solve_s = now_s() - t_start;
   }
   return PDNQP_OK;
 }
@@ -886,6 +984,130 @@ int Solver::kernel_stats(pdnqp_kernel_stat *out, int32_t cap, int32_t *count) co
     out[k].avg_us = timers_[k].launches ? 1000.0 * timers_[k].total_ms / timers_[k].launches : 0.0;
     out[k].bytes_per_launch = timers_[k].bytes;
   }
+  return PDNQP_OK;
+}
+
+// ===========================================================================
+// Batched path (pdnqp_batch.hip runs the method; these prepare and collect).
+// ===========================================================================
+int Solver::batch_prepare(double eps_abs, double eps_rel, const double *x0, const double *lam0,
+                          int block, double ticks_per_s, BatchOut *dev_out, BatchInst &bi,
+                          std::string &err) {
+  const int32_t n = qp_.n, m = qp_.m;
+  std::vector<double> x0c, lam0i;
+  int r = begin(x0, lam0, x0c, lam0i, err);
+  if (r) return r;
+  hipError_t e = hipMemcpyAsync(v_.X[0], x0c.data(), n * 8, hipMemcpyHostToDevice, stream_);
+  if (m && e == hipSuccess)
+    e = hipMemcpyAsync(v_.lam, lam0i.data(), m * 8, hipMemcpyHostToDevice, stream_);
+  if ((r = check(e, "upload x0/lambda0", err))) return r;
+  // row blocks of the launch's tile
+  const int tile = batch_tile(block);
+  BatchBlocks *bb = nullptr;
+  for (auto &x : bblocks_)
+    if (x.tile == tile) bb = &x;
+  if (!bb) {
+    BatchBlocks nb;
+    nb.tile = tile;
+    auto build = [&](const std::vector<int32_t> &rp, int32_t rows, int32_t *&dev,
+                     int32_t &nrb) -> bool {
+      std::vector<int32_t> rb(rows + 2);
+      stream_row_blocks(rp.data(), rows, 4 * block, &nrb, rb.data(), tile);
+      dev = (int32_t *)dalloc((size_t)(nrb + 1) * 4);
+      if (!dev) return false;
+      return hipMemcpyAsync(dev, rb.data(), (size_t)(nrb + 1) * 4, hipMemcpyHostToDevice,
+                            stream_) == hipSuccess;
+    };
+    if (!build(qp_.Qp, n, nb.q, nb.nq) || !build(qp_.Qop, n, nb.qo, nb.nqo) ||
+        !build(qp_.Ap, m, nb.a, nb.na) || !build(qp_.ATp, n, nb.at, nb.nat)) {
+      err = "batch row-block upload failed";
+      return PDNQP_E_DEVICE;
+    }
+    bblocks_.push_back(nb);
+    bb = &bblocks_.back();
+  }
+  if (!lz_) {
+    lz_ = (double *)dalloc((size_t)2 * std::max(1, st_.lanczos_iters) * 8);
+    if (!lz_) {
+      err = "device allocation failed";
+      return PDNQP_E_NOMEM;
+    }
+  }
+  std::memset(&bi, 0, sizeof(bi));
+  bi.n = n;
+  bi.m = m;
+  bi.me = qp_.me;
+  bi.mi = qp_.mi;
+  bi.st = st_;
+  bi.eps_abs = eps_abs;
+  bi.eps_rel = eps_rel;
+  // an infinite limit becomes 3600 s: every workgroup of the launch ends
+  const double lim = std::isfinite(st_.time_limit_s) ? std::min(st_.time_limit_s, 1e9) : 3600.0;
+  bi.limit_ticks = (uint64_t)(lim * ticks_per_s);
+  bi.Q = BCsr{Qp_, Qi_, bb->q, n, bb->nq};
+  bi.Qo = BCsr{Qop_, Qoi_, bb->qo, n, bb->nqo};
+  bi.A = BCsr{Ap_, Ai_, bb->a, m, bb->na};
+  bi.AT = BCsr{ATp_, ATi_, bb->at, n, bb->nat};
+  bi.atperm = atperm_;
+  bi.Qraw = Qraw_;
+  bi.Qoraw = Qoraw_;
+  bi.qdiag_raw = qdiag_raw_;
+  bi.Araw = Araw_;
+  bi.ATraw = ATraw_;
+  bi.craw = craw_;
+  bi.xlraw = xlraw_;
+  bi.xuraw = xuraw_;
+  bi.braw = braw_;
+  bi.Qv = Qv_;
+  bi.Qov = Qov_;
+  bi.qdiag = qdiag_;
+  bi.Av = Av_;
+  bi.ATv = ATv_;
+  bi.c = c_;
+  bi.lo = lo_;
+  bi.hi = hi_;
+  bi.b = b_;
+  bi.Qo32 = Qo32v_;
+  bi.A32 = A32v_;
+  bi.AT32 = AT32v_;
+  bi.v = v_;
+  bi.Fx2 = Fx2_;
+  bi.Fs2 = Fs2_;
+  bi.Fr2 = Fr2_;
+  bi.E2buf = E2buf_;
+  bi.lz = lz_;
+  bi.w64 = iv64();
+  bi.w32 = iv32_;
+  bi.out = dev_out;
+  return check(hipStreamSynchronize(stream_), "batch prepare", err);
+}
+
+int Solver::batch_finish(const BatchOut &o, double ticks_per_s, double *x_out, double *lam_out,
+                         pdnqp_info *info, std::string &err) {
+  Outcome oc;
+  oc.status = o.status;
+  oc.outer_iters = o.outer_iters;
+  oc.trials = o.trials;
+  oc.accepted = o.accepted;
+  oc.rejected = o.rejected;
+  oc.restarts = o.restarts;
+  oc.checks = o.checks;
+  oc.rp = o.rp;
+  oc.rd = o.rd;
+  oc.sp = o.sp;
+  oc.sd = o.sd;
+  oc.gamma = o.gamma;
+  oc.lam_hat = o.lam_hat;
+  oc.omega = o.omega;
+  oc.c_obj = o.c_obj;
+  oc.setup_s = (double)(o.t_setup - o.t_begin) / ticks_per_s;
+  oc.trace_iters = o.trace_iters_n;
+  oc.trace_trials = o.trace_trials_n;
+  oc.trace_checks = o.trace_checks_n;
+  gamma_ = o.gamma;
+  const int r = finish(oc, x_out, lam_out, info, err);
+  if (r) return r;
+  if (info) info->solve_s = (double)(o.t_end - o.t_begin) / ticks_per_s;
   return PDNQP_OK;
 }
 

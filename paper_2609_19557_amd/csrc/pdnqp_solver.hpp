@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/pdnqp.h"
+#include "pdnqp_batch.hpp"
 #include "pdnqp_kernels.hpp"
 
 namespace pdnqp {
@@ -40,6 +41,15 @@ struct KernelTimer {
   double bytes = 0.0;
 };
 
+// What a solve reports besides the vectors (filled by either path).
+struct Outcome {
+  int status = PDNQP_MAX_ITER;
+  int64_t outer_iters = 0, trials = 0, accepted = 0, rejected = 0, restarts = 0, checks = 0;
+  double rp = 0, rd = 0, sp = 0, sd = 0, gamma = 0, lam_hat = 0, omega = 0, c_obj = 1;
+  double setup_s = 0;
+  int32_t trace_iters = 0, trace_trials = 0, trace_checks = 0;
+};
+
 class Solver {
  public:
   Solver() = default;
@@ -53,6 +63,17 @@ class Solver {
   int kernel_stats(pdnqp_kernel_stat *out, int32_t cap, int32_t *count) const;
   const HostQP &qp() const { return qp_; }
   int dw() const { return qp_.n + qp_.mi + qp_.m; }
+  int precision() const { return st_.precision; }
+  int device() const { return device_; }
+  hipStream_t stream() const { return stream_; }
+  // Batched path: fills the instance descriptor (uploads the start point,
+  // builds the row blocks of the launch's tile) and, after the kernel,
+  // copies the result back like solve does.
+  int batch_prepare(double eps_abs, double eps_rel, const double *x0, const double *lam0,
+                    int block, double ticks_per_s, BatchOut *dev_out, BatchInst &bi,
+                    std::string &err);
+  int batch_finish(const BatchOut &o, double ticks_per_s, double *x_out, double *lam_out,
+                   pdnqp_info *info, std::string &err);
 
  private:
   void *dalloc(size_t bytes);
@@ -70,10 +91,14 @@ class Solver {
   void form_inner(double gamma);
   void ruiz_outer();
   double lanczos(std::string &err, bool &ok);
-  void timed_launch(int which, const std::function<void()> &f);
+  void timed_launch(int which, const std::function<void(LaunchEvents)> &f);
   void harvest_timers();
   void external_check(const std::vector<double> &x, const std::vector<double> &lam,
                       pdnqp_info *info) const;
+  int begin(const double *x0, const double *lam0, std::vector<double> &x0c,
+            std::vector<double> &lam0i, std::string &err);
+  int finish(const Outcome &oc, double *x_out, double *lam_out, pdnqp_info *info,
+             std::string &err);
 
   HostQP qp_;
   pdnqp_settings st_{};
@@ -117,6 +142,41 @@ class Solver {
   bool traced_ = false;
   // profiling
   std::vector<KernelTimer> timers_;
+  int64_t chunk_count_ = 0;
+  // captured chunk of the current outer step (settings.graph)
+  hipGraphExec_t gexec_ = nullptr;
+  hipStream_t cap_stream_ = nullptr;
+  bool graph_valid_ = false;
+  template <typename T>
+  void enqueue_chunk(int slots, bool sampled, const IterVecs<T> &iv, const CsrT<T> &Qo,
+                     const CsrT<T> &A, const CsrT<T> &AT);
+  template <typename T>
+  int capture_chunk(std::string &err, const IterVecs<T> &iv, const CsrT<T> &Qo, const CsrT<T> &A,
+                    const CsrT<T> &AT);
+  // batched path: row blocks per tile size (Q, Q_off, A, A'), Lanczos coefficients
+  struct BatchBlocks {
+    int tile = 0;
+    int32_t *q = nullptr, *qo = nullptr, *a = nullptr, *at = nullptr;
+    int32_t nq = 0, nqo = 0, na = 0, nat = 0;
+  };
+  std::vector<BatchBlocks> bblocks_;
+  double *lz_ = nullptr;
+  int device_ = 0;
 };
+
+// Batched persistent solve over several handles (pdnqp_batch_host.cpp).
+struct BatchRequest {
+  std::vector<Solver *> solvers;
+  double eps_abs = 1e-4, eps_rel = 1e-4;
+  double *const *x_out = nullptr;
+  double *const *lam_out = nullptr;
+  pdnqp_info *infos = nullptr;
+  int block = 0;        // 0: tuned or default
+  int probe_inner = 0;  // > 0: tuning probe (one outer step, this many inner iterations)
+};
+int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<double> *done_ms,
+              std::string &err);
+int autotune_batch(const BatchRequest &req, int32_t *block_out, double *ms_out, std::string &err);
+void set_batch_block(int block);
 
 }  // namespace pdnqp

@@ -64,7 +64,7 @@ class Settings(ctypes.Structure):
         ("verbose", ctypes.c_int32),
         ("center_floor", ctypes.c_int32),
         ("precision", ctypes.c_int32),
-        ("reserved1", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),
@@ -114,9 +114,25 @@ class KernelStat(ctypes.Structure):
     ]
 
 
+class BatchReport(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32),
+        ("staged", ctypes.c_int32),
+        ("tuned", ctypes.c_int32),
+        ("kernel_ms", ctypes.c_double),
+        ("prepare_s", ctypes.c_double),
+        ("finish_s", ctypes.c_double),
+        ("wall_s", ctypes.c_double),
+    ]
+
+
 EXPORTED = ["pdnqp_default_settings", "pdnqp_settings_size", "pdnqp_info_size", "pdnqp_create",
             "pdnqp_solve", "pdnqp_solve_batch", "pdnqp_destroy", "pdnqp_last_error",
-            "pdnqp_dims", "pdnqp_get_trace", "pdnqp_kernel_stats"]
+            "pdnqp_dims", "pdnqp_get_trace", "pdnqp_kernel_stats", "pdnqp_batch_last_report",
+            "pdnqp_batch_set_block", "pdnqp_batch_autotune"]
 
 _lib = None
 
@@ -158,6 +174,12 @@ def load(path=None):
     lib.pdnqp_get_trace.restype = ctypes.c_int
     lib.pdnqp_kernel_stats.argtypes = [vp, P(KernelStat), i32, P(i32)]
     lib.pdnqp_kernel_stats.restype = ctypes.c_int
+    lib.pdnqp_batch_last_report.argtypes = [P(BatchReport), vp, i32]
+    lib.pdnqp_batch_last_report.restype = ctypes.c_int
+    lib.pdnqp_batch_set_block.argtypes = [i32]
+    lib.pdnqp_batch_set_block.restype = ctypes.c_int
+    lib.pdnqp_batch_autotune.argtypes = [i32, P(vp), i32, P(i32), vp]
+    lib.pdnqp_batch_autotune.restype = ctypes.c_int
     if lib.pdnqp_settings_size() != ctypes.sizeof(Settings):
         raise ImportError("pdnqp_settings layout mismatch between library and binding")
     if lib.pdnqp_info_size() != ctypes.sizeof(Info):
@@ -312,7 +334,8 @@ class Solver:
 
 
 def solve_batch(solvers, eps_abs=1e-4, eps_rel=1e-4):
-    """``pdnqp_solve_batch`` over a list of ``Solver``s."""
+    """``pdnqp_solve_batch`` over a list of ``Solver``s (one persistent
+    kernel launch; see ``batch_report`` for its configuration and timing)."""
     lib = load()
     k = len(solvers)
     xs = [np.zeros(s.n) for s in solvers]
@@ -325,3 +348,42 @@ def solve_batch(solvers, eps_abs=1e-4, eps_rel=1e-4):
     if code != OK:
         raise _err(lib, code)
     return [(xs[i], ls[i][:solvers[i].m], infos[i].as_dict()) for i in range(k)]
+
+
+def batch_report(count=None):
+    """Report of the last ``solve_batch`` on this thread: launch configuration,
+    kernel and host times, and each instance's finish time (ms after the
+    first instance started)."""
+    lib = load()
+    rep = BatchReport()
+    cap = count if count is not None else 0
+    done = np.zeros(max(cap, 1))
+    code = lib.pdnqp_batch_last_report(ctypes.byref(rep), _ptr(done) if cap else None, cap)
+    if code != OK:
+        raise _err(lib, code)
+    d = {name: getattr(rep, name) for name, _ in rep._fields_}
+    if cap:
+        d["done_ms"] = done[:min(cap, rep.count)].copy()
+    return d
+
+
+def batch_set_block(block):
+    """Workgroup size of later batched solves (256, 512, 1024; 0 = tuned)."""
+    lib = load()
+    code = lib.pdnqp_batch_set_block(int(block))
+    if code != OK:
+        raise _err(lib, code)
+
+
+def batch_autotune(solvers, probe_inner=64):
+    """Times each workgroup size on the batch (short probe) and caches the
+    fastest for the batch's class; returns (block, [ms for 256, 512, 1024])."""
+    lib = load()
+    k = len(solvers)
+    hs = (ctypes.c_void_p * k)(*[s.h.value for s in solvers])
+    blk = ctypes.c_int32()
+    ms = np.zeros(3)
+    code = lib.pdnqp_batch_autotune(k, hs, int(probe_inner), ctypes.byref(blk), _ptr(ms))
+    if code != OK:
+        raise _err(lib, code)
+    return blk.value, ms.tolist()

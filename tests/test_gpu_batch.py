@@ -1,0 +1,187 @@
+"""GPU parity of the batched persistent solve (pdnqp_solve_batch: one kernel
+launch, one workgroup per instance at a time) against the FP64 CPU oracle,
+instance by instance, on uneven batches drawn like the batched workload
+(n_i ~ U{lo..hi}, m_i = n_i // 2, k_R = 5, k_A = 4).
+
+FP64: the first accepted iterations of every instance match the oracle's at
+1e-9 relative, with identical accept/reject and check decisions inside that
+window, for each workgroup size.  Full solves: same status as the oracle,
+termination test met, reported KKT residuals those of the returned point.
+FP32 bulk: iterates track the oracle at 1e-4 over the first iterations and
+the instances solve to the tolerance.
+"""
+
+import numpy as np
+import pytest
+
+import qpgen
+from oracle import pdnqp_oracle as O
+from tests.test_gpu_parity import (EDGE, _gpu_kwargs, assert_decision_parity,
+                                   assert_iterate_parity, window_of)
+
+pytestmark = pytest.mark.gpu
+
+ITERS = 300
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_19557_amd as P
+    P.load()
+    return P
+
+
+def _batch(seed, count, lo, hi):
+    sizes = qpgen.batch_sizes(seed, count, lo, hi)
+    return [qpgen.random_indefinite_qp(int(n), int(n) // 2, 5, 4, seed, instance=i)
+            for i, n in enumerate(sizes)]
+
+
+@pytest.fixture(scope="module")
+def parity_case():
+    probs = _batch(7, 5, 200, 1200)
+    st = O.Settings(max_outer=8, outer_scaling=2)
+    traces = []
+    for p in probs:
+        tr = O.Trace(max_iters=ITERS)
+        O.solve(p, st, trace=tr)
+        traces.append(tr)
+    return probs, st, traces
+
+
+def _solve_batch(P, probs, st, block=0, **kw):
+    solvers = [P.Solver.from_problem(p, **_gpu_kwargs(st), **kw) for p in probs]
+    P.batch_set_block(block)
+    try:
+        out = P.solve_batch(solvers, st.eps_abs, st.eps_rel)
+    finally:
+        P.batch_set_block(0)
+    return solvers, out, P.batch_report(len(probs))
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_batch_fp64_iterates_match_oracle(P, parity_case, block):
+    probs, st, traces = parity_case
+    solvers, out, rep = _solve_batch(P, probs, st, block, trace_iters=ITERS,
+                                     trace_trials=4 * ITERS)
+    assert rep["block"] == block and rep["count"] == len(probs)
+    assert rep["staged"] == len(probs)  # small instances fit in LDS
+    for k, (p, s, tr) in enumerate(zip(probs, solvers, traces)):
+        t = s.trace()
+        assert_iterate_parity(tr, t, n_expect=min(ITERS, len(tr.w)))
+        assert_decision_parity(tr, t, window_of(tr))
+        assert out[k][2]["gamma"] == pytest.approx(tr_gamma(p, st), rel=1e-10)
+
+
+_GAMMA = {}
+
+
+def tr_gamma(p, st):
+    key = (p["n"], p["seed"], p.get("instance"))
+    if key not in _GAMMA:
+        _GAMMA[key] = O.solve(p, O.Settings(max_outer=0, outer_scaling=st.outer_scaling)).gamma
+    return _GAMMA[key]
+
+
+def test_batch_fp64_unstaged_matches_oracle(P, parity_case):
+    """An instance too large to stage in LDS runs with global gathers; its
+    first iterations still match the oracle."""
+    prob = qpgen.random_indefinite_qp(30000, 15000, 5, 4, 3, instance=0)
+    st = O.Settings(max_outer=2, max_inner=80, outer_scaling=2)
+    tr = O.Trace(max_iters=60)
+    O.solve(prob, st, trace=tr)
+    solvers, out, rep = _solve_batch(P, [prob], st, 256, trace_iters=60, trace_trials=200)
+    assert rep["staged"] == 0
+    t = solvers[0].trace()
+    assert_iterate_parity(tr, t, n_expect=60)
+    assert_decision_parity(tr, t, window_of(tr))
+
+
+def test_batch_fp64_full_solves(P):
+    probs = _batch(11, 4, 200, 700)
+    st = O.Settings(outer_scaling=2, max_outer=5000, time_limit=120.0)
+    solvers, out, rep = _solve_batch(P, probs, st)
+    for p, (x, lam, info) in zip(probs, out):
+        res_o = O.solve(p, st)
+        assert info["status"] == res_o.status == O.SOLVED
+        assert info["r_p_scaled"] <= 1e-4 + 1e-4 * info["s_p_scaled"]
+        assert info["r_d_scaled"] <= 1e-4 + 1e-4 * info["s_d_scaled"]
+        rp, rd, _, _ = O.external_kkt(p, x, lam)
+        assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
+        assert info["r_d"] == pytest.approx(rd, rel=1e-6, abs=1e-12)
+        assert np.all(x >= p["xl"]) and np.all(x <= p["xu"])
+        assert 0 < info["setup_s"] <= info["solve_s"]
+    done = P.batch_report(len(probs))["done_ms"]
+    assert np.all(done > 0)
+
+
+def test_batch_edge_cases(P):
+    """All edge-case problems (no rows, equalities only, two-sided rows,
+    empty rows with free variables, one variable, ragged tails) in one
+    launch; each follows the oracle's trajectory and ends like it."""
+    names = sorted(EDGE)
+    probs = [EDGE[k] for k in names]
+    st = O.Settings(max_outer=12, outer_scaling=2)
+    solvers, out, rep = _solve_batch(P, probs, st, trace_iters=400, trace_trials=800)
+    for name, p, s, (x, lam, info) in zip(names, probs, solvers, out):
+        tr = O.Trace(max_iters=400)
+        res_o = O.solve(p, st, trace=tr)
+        t = s.trace()
+        assert_iterate_parity(tr, t)
+        assert_decision_parity(tr, t, window_of(tr))
+        assert info["status"] == res_o.status, name
+        np.testing.assert_allclose(x, res_o.x, atol=1e-8 * max(1, np.abs(res_o.x).max()),
+                                   err_msg=name)
+
+
+def test_batch_limits(P):
+    """Outer-iteration, inner-iteration and time limits end each instance
+    (and so the launch); the inner limit continues the outer loop."""
+    probs = _batch(5, 3, 300, 600)
+    st = O.Settings(max_inner=5, max_outer=30)
+    solvers, out, rep = _solve_batch(P, probs, st, trace_iters=150, trace_trials=400)
+    for p, s, (x, lam, info) in zip(probs, solvers, out):
+        tr = O.Trace(max_iters=150)
+        res_o = O.solve(p, st, trace=tr)
+        assert_iterate_parity(tr, s.trace())
+        assert info["status"] == res_o.status == O.MAX_ITER
+        assert info["outer_iters"] == 30
+    st2 = O.Settings(time_limit=0.0)
+    _, out2, _ = _solve_batch(P, probs, st2)
+    assert all(o[2]["status"] == O.TIME_LIMIT for o in out2)
+
+
+def test_batch_fp32_tracks_oracle_and_solves(P):
+    probs = _batch(13, 4, 200, 900)
+    st = O.Settings(outer_scaling=2, max_outer=5000, time_limit=120.0)
+    solvers, out, rep = _solve_batch(P, probs, st, precision=P.FP32, trace_iters=40)
+    for p, s, (x, lam, info) in zip(probs, solvers, out):
+        tr = O.Trace(max_iters=40)
+        O.solve(p, O.Settings(outer_scaling=2, max_outer=3), trace=tr)
+        t = s.trace()
+        for k in range(30):
+            wn = max(1.0, np.abs(tr.w[k]).max())
+            assert np.abs(t["w"][k] - tr.w[k]).max() / wn <= 1e-4, f"w at {k}"
+        assert info["status"] == O.SOLVED
+        rp, rd, _, _ = O.external_kkt(p, x, lam)
+        assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
+
+
+def test_batch_rejects_mixed_precision(P):
+    probs = _batch(2, 2, 200, 300)
+    a = P.Solver.from_problem(probs[0], time_limit_s=10.0)
+    b = P.Solver.from_problem(probs[1], precision=P.FP32, time_limit_s=10.0)
+    with pytest.raises(P.PdnqpError, match="precision"):
+        P.solve_batch([a, b])
+
+
+def test_batch_autotune_caches_choice(P):
+    probs = _batch(17, 8, 200, 2000)
+    solvers = [P.Solver.from_problem(p, time_limit_s=60.0) for p in probs]
+    block, ms = P.batch_autotune(solvers, probe_inner=32)
+    assert block in (256, 512, 1024) and len(ms) == 3 and min(ms) > 0
+    assert ms[(256, 512, 1024).index(block)] == min(ms)
+    out = P.solve_batch(solvers)
+    rep = P.batch_report(len(probs))
+    assert rep["tuned"] == 1 and rep["block"] == block
+    assert all(np.all(np.isfinite(x)) for x, _, _ in out)

@@ -262,3 +262,25 @@ def test_medium_first_iterations_sampled(P, seed):
     res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, iters=150, trials=300)
     assert_iterate_parity(tr, t, n_expect=128)
     assert_decision_parity(tr, t, window_of(tr))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_stream_launches(P, precision):
+    """With settings.graph the chunk of each outer step is captured once and
+    replayed (with host reads of the control block between replays, and a
+    new capture at every outer step); it runs the same kernels in the same
+    order, so traces and results equal those of plain launches bit for bit."""
+    prob = qpgen.workload("small", 2)
+    st = _oracle_settings(max_outer=25, outer_scaling=2)
+    outs = []
+    for g in (0, 1):
+        s = P.Solver.from_problem(prob, precision=precision, graph=g, trace_iters=500,
+                                  trace_trials=2000, **_gpu_kwargs(st))
+        x, lam, info = s.solve(st.eps_abs, st.eps_rel)
+        outs.append((x, lam, info, s.trace()))
+    (x0, l0, i0, t0), (x1, l1, i1, t1) = outs
+    assert i0["outer_iters"] == i1["outer_iters"] and i0["outer_iters"] > 3
+    assert i0["inner_trials"] == i1["inner_trials"]
+    for key in ("w", "y", "trials", "checks"):
+        assert np.array_equal(t0[key], t1[key]), key
+    assert np.array_equal(x0, x1) and np.array_equal(l0, l1)
