@@ -91,6 +91,59 @@ def cpu_baseline(prob, n_inner):
                        f"products (OMP_NUM_THREADS={threads})")}
 
 
+def batch_leg(P, qpgen, args):
+    """Batched workload: ``count`` uneven instances (n_i ~ U{200..20000},
+    m_i = n_i // 2, k_R = 5, k_A = 4) solved to 1e-4 in one persistent
+    launch (FP32 bulk, FP64 reductions), each under a time limit; the
+    workgroup size comes from the autotuner.  Baseline: a sample of the same
+    instances solved one after another by the FP64 single-instance path."""
+    import numpy as np
+    probs = qpgen.batch(args.seed, args.batch_count)
+    kw = dict(time_limit_s=args.batch_limit, outer_scaling=P.SCALE_RUIZ_QA)
+    solvers = [P.Solver.from_problem(p, precision=P.FP32, **kw) for p in probs]
+    cfg, tune_ms = P.batch_autotune(solvers, probe_inner=64)
+    t0 = time.perf_counter()
+    out = P.solve_batch(solvers, 1e-4, 1e-4)
+    wall = time.perf_counter() - t0
+    rep = P.batch_report(len(probs))
+    done = rep.pop("done_ms")
+    status = np.array([o[2]["status"] for o in out])
+    solve_s = np.array([o[2]["solve_s"] for o in out])
+    inner = np.array([o[2]["inner_accepted"] for o in out])
+    ok = status == P.SOLVED
+    for s in solvers:
+        s.close()
+    idx = np.linspace(0, len(probs) - 1, max(1, args.batch_seq_sample)).astype(int)
+    seq = []
+    for i in idx:
+        s = P.Solver.from_problem(probs[i], precision=P.FP64, **kw)
+        t1 = time.perf_counter()
+        _, _, inf = s.solve(1e-4, 1e-4)
+        seq.append((time.perf_counter() - t1, inf["status"] == P.SOLVED))
+        s.close()
+    seq_t = np.array([t for t, _ in seq])
+    return {
+        "workload": (f"{len(probs)} instances, n_i ~ U{{200..20000}} (sum n {sum(p['n'] for p in probs):,}), "
+                     f"m_i = n_i // 2, k_R = 5, k_A = 4, seed {args.seed}"),
+        "precision": "fp32 bulk, fp64 reductions", "tol": 1e-4, "outer_scaling": "ruiz_qa",
+        "time_limit_per_instance_s": args.batch_limit,
+        "block": rep["block"], "waves": rep["waves"], "grid": rep["grid"],
+        "lds_bytes": rep["lds_bytes"], "staged": rep["staged"],
+        "autotune_ms": {f"{b}x{w}": round(x, 1) for (b, w), x in zip(P.BATCH_CONFIGS, tune_ms)},
+        "wall_s": round(wall, 3), "kernel_ms": round(rep["kernel_ms"], 1),
+        "solved": int(ok.sum()),
+        "done_ms_p50": round(float(np.percentile(done, 50)), 1),
+        "done_ms_p99": round(float(np.percentile(done, 99)), 1),
+        "solve_s_p50": round(float(np.percentile(solve_s, 50)), 3),
+        "solve_s_p99": round(float(np.percentile(solve_s, 99)), 3),
+        "solved_solve_s_p50": round(float(np.percentile(solve_s[ok], 50)), 3) if ok.any() else None,
+        "inner_iters_per_s_aggregate": round(float(inner.sum()) / max(1e-9, wall), 1),
+        "sequential_fp64_sample": {"instances": len(seq), "mean_s": round(float(seq_t.mean()), 3),
+                                   "solved": int(sum(ok_ for _, ok_ in seq)),
+                                   "estimate_all_s": round(float(seq_t.mean()) * len(probs), 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +158,13 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32",
                     help="fp32: FP32 matrix values and inner vectors with FP64 reductions, FP64 "
                          "outer update and final check (the large workload's stated arithmetic)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched workload (512 uneven instances, one persistent launch)")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-limit", type=float, default=30.0,
+                    help="time limit per instance of the batched workload (s)")
+    ap.add_argument("--batch-seq-sample", type=int, default=8,
+                    help="instances of the batch solved one after another in FP64 as baseline")
     ap.add_argument("--no-other-precision", action="store_true",
                     help="skip timing the other precision on the same instance")
     args = ap.parse_args()
@@ -215,6 +275,11 @@ def main():
         cpu = cpu_baseline(prob, args.cpu_iters)
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_leg(P, qpgen, args)
+        print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
+
     value = info["inner_accepted"] / wall
     out = {
         "metric": METRIC,
@@ -240,6 +305,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
         "other_precision": other,
+        "batch": batch,
         "trial": {"us_per_trial_kernels": round(trial_us, 3),
                   "bytes_per_trial": trial_bytes,
                   "GBps_per_trial": round(trial_bytes / (trial_us * 1e-6) / 1e9, 1)

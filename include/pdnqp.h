@@ -67,6 +67,9 @@ enum {
   PDNQP_FP32 = 1
 };
 
+/* Largest Anderson memory (settings.anderson_mem). */
+enum { PDNQP_ANDERSON_MAX = 8 };
+
 /* Solver parameters.  Obtain defaults with pdnqp_default_settings() and
  * override fields.  Fields marked [paper] take the defaults of the paper's
  * parameter table; fields marked [reading] fix points the paper leaves
@@ -111,6 +114,11 @@ typedef struct pdnqp_settings {
   int32_t graph;           /* 1: each outer step captures its chunk of trial slots and the check
                               in a hipGraph and replays it (same kernels, same results); 0 (default):
                               plain stream launches */
+  int32_t anderson_mem;    /* memory m_A of the Anderson acceleration of (lambda_E, lambda_I, z)
+                              (Section 3.2, "Anderson acceleration"; the paper's table: 5);
+                              0 (default): off; at most PDNQP_ANDERSON_MAX */
+  double anderson_reg;     /* [reading] Tikhonov weight of the Anderson least-squares problem,
+                              relative to the mean diagonal of its Gram matrix; 1e-10 */
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */
@@ -122,7 +130,7 @@ typedef struct pdnqp_settings {
 /* Per-solve report. */
 typedef struct pdnqp_info {
   int32_t status;          /* PDNQP_SOLVED ... */
-  int32_t reserved;
+  int32_t anderson_steps;  /* outer steps that took an Anderson extrapolation */
   int64_t outer_iters;     /* outer iterations performed */
   int64_t inner_trials;    /* trial steps (accepted + rejected) */
   int64_t inner_accepted;  /* accepted inner iterations */
@@ -219,7 +227,9 @@ typedef struct pdnqp_batch_report {
   int32_t grid;        /* workgroups launched (resident at once) */
   int32_t lds_bytes;   /* dynamic LDS per workgroup */
   int32_t staged;      /* instances whose gathered vectors were staged in LDS */
-  int32_t tuned;       /* 1: block size taken from the autotuner's cache */
+  int32_t tuned;       /* 1: configuration taken from the autotuner's cache */
+  int32_t waves;       /* minimum waves per SIMD the kernel was built for (1 or 4) */
+  int32_t reserved;
   double kernel_ms;    /* the persistent kernel (HIP events on the stream) */
   double prepare_s;    /* host: start points, descriptors, uploads */
   double finish_s;     /* host: copies back, unscaling, external KKT checks */
@@ -231,19 +241,24 @@ typedef struct pdnqp_batch_report {
  * the first instance started (device clock). */
 int pdnqp_batch_last_report(pdnqp_batch_report *rep, double *done_ms, int32_t cap);
 
-/* Workgroup size for later batched solves in this process: 256, 512 or
- * 1024; 0 returns to the autotuned choice (256 when none is cached). */
-int pdnqp_batch_set_block(int32_t block);
+/* Launch configuration for later batched solves in this process: the
+ * workgroup size (256, 512, 1024) and the minimum waves per SIMD the kernel
+ * variant was built for (1: the compiler's register budget; 4: at most 128
+ * registers, more workgroups per CU).  Available pairs: (256,1), (512,1),
+ * (1024,1), (256,4), (512,4).  block = 0 returns to the autotuned choice
+ * ((256,1) when none is cached). */
+int pdnqp_batch_set_config(int32_t block, int32_t waves);
 
-/* Autotuner of the batched solve: runs the batch once per workgroup size
+/* Autotuner of the batched solve: runs the batch once per configuration
  * with a short budget per instance (one outer step of at most
- * `probe_inner` accepted inner iterations), keeps the fastest size for the
+ * `probe_inner` accepted inner iterations), keeps the fastest for the
  * batch's class (precision, count and mean nonzeros per instance, each
  * rounded down to a power of two) in a process-wide cache that
- * pdnqp_solve_batch consults, and returns it in *block_out.  ms_out
- * (optional, 3 entries) receives the kernel time of 256, 512 and 1024. */
+ * pdnqp_solve_batch consults, and returns it in *block_out, *waves_out.
+ * ms_out (optional, 5 entries) receives the kernel time of each
+ * configuration in the order listed above. */
 int pdnqp_batch_autotune(int32_t count, pdnqp_solver *const *solvers, int32_t probe_inner,
-                         int32_t *block_out, double *ms_out);
+                         int32_t *block_out, int32_t *waves_out, double *ms_out);
 
 /* Releases the handle and its device memory.  NULL is a no-op. */
 void pdnqp_destroy(pdnqp_solver *s);

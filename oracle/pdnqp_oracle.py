@@ -102,6 +102,12 @@ class Settings:
     # test knob: multiplies the diagonal steps at every rebuild (1 = paper)
     step_boost: float = 1.0
     outer_scaling: int = 0
+    # Anderson acceleration of (lambda_E, lambda_I, z) (Section 3.2,
+    # "Anderson acceleration"): memory m_A (the paper's table: 5; 0 = off)
+    anderson_mem: int = 0
+    # [reading] Tikhonov weight of the Anderson least-squares problem,
+    # relative to the mean diagonal of its Gram matrix
+    anderson_reg: float = 1e-10
 
 
 # ---------------------------------------------------------------------------
@@ -649,6 +655,36 @@ def inner_solve(state: InnerState, omega, delta_a, delta_r, st: Settings,
 # Outer loop (Algorithm "practical outer iteration")
 # ---------------------------------------------------------------------------
 
+def anderson_step(U, G, reg):
+    """Classical Type-II Anderson extrapolation (Anderson 1965), as the
+    paper applies it to the outer duals and the proximal centre (Section
+    3.2, "Anderson acceleration").
+
+    U[0..p] are the most recent points at which the outer map was evaluated
+    (oldest first) and G[0..p] their images.  With residuals f_j = G_j - U_j
+    and differences dF_j = f_{j+1} - f_j, dG_j = G_{j+1} - G_j,
+        gamma = argmin ||f_p - dF gamma||_2,   next point = G_p - dG gamma.
+    The least-squares problem is solved through its normal equations with a
+    Tikhonov term reg * mean(diag(dF'dF)) [reading]; an exactly singular
+    system (every difference zero) gives gamma = 0.  p = 0 gives G_0 (the
+    plain iteration)."""
+    p = len(U) - 1
+    if p <= 0:
+        return np.array(G[-1], dtype=float, copy=True)
+    F = [np.asarray(G[j], float) - np.asarray(U[j], float) for j in range(p + 1)]
+    dF = np.column_stack([F[j + 1] - F[j] for j in range(p)])
+    dG = np.column_stack([np.asarray(G[j + 1], float) - np.asarray(G[j], float)
+                          for j in range(p)])
+    M = dF.T @ dF
+    rhs = dF.T @ F[p]
+    tik = reg * float(np.trace(M)) / p
+    try:
+        gamma = np.linalg.solve(M + tik * np.eye(p), rhs)
+    except np.linalg.LinAlgError:   # all differences zero: the plain point
+        gamma = np.zeros(p)
+    return np.asarray(G[p], float) - dG @ gamma
+
+
 def multiplier_update(S: Scaled, x, lam, sigma):
     """eq. (practical-multiplier-update): s_I = max{b_I, A_I x + lam_I / sigma_I},
     lam_E += sigma_E (A_E x - b_E), lam_I = min{0, lam_I + sigma_I (A_I x - b_I)}.
@@ -693,6 +729,7 @@ class Result:
     scaled_lam: np.ndarray = None
     sigma: np.ndarray = None
     omega: float = math.nan
+    anderson_steps: int = 0
 
 
 def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
@@ -727,8 +764,14 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
     status = MAX_ITER
     k = 0
     rp = rd = sp_ = sd = math.nan
+    aa_u, aa_g = [], []       # Anderson history: points and their images
+    aa_last = None            # residuals at the last extrapolation
+    aa_steps = 0
+    rd_prev = None            # r_d of the previous outer step
+    u_form = None
     while k < st.max_outer:
         if state is None:
+            u_form = np.concatenate([lam, z])
             qp = form_inner_qp(S, z, lam, sigma, gamma)
             si = scale_inner(qp, sigma, st)
             w0 = warm_start(S, x, lam, sigma)
@@ -762,6 +805,7 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
             break
         # row-wise penalty update, eq. (penalty-trigger-eq)
         r_row = np.concatenate([ax[:me] - S.b[:me], ax[me:] - s_new])
+        sigma_before = sigma
         if r_prev is not None:
             rn = _ninf(r_row)
             active = np.concatenate([np.ones(me, bool), lam[me:] < 0.0])
@@ -772,6 +816,7 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
                 fac = np.maximum(1.0, st.sigma_growth * np.abs(r_row) / rn)
                 sigma = np.where(trig, np.minimum(st.sigma_max, sigma * fac), sigma)
         r_prev = r_row
+        penalties_moved = bool(np.any(sigma != sigma_before))
         # eq. (inner-tolerance-factor); [reading] ratio 1 when r_d = 0,
         # tolerances floored at the outer tolerances
         dxz = _ninf(x_new - z)
@@ -787,6 +832,16 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
             if st.center_floor:
                 eps_ak = max(eps_ak, st.eps_abs)
                 eps_rk = max(eps_rk, st.eps_rel)
+        # Anderson step on (lambda_E, lambda_I, z), Section 3.2
+        if st.anderson_mem > 0:
+            lam, z, aa_last = _anderson_outer(st, S, me, u_form, lam, z, rp, rd, sp_,
+                                              penalties_moved, aa_u, aa_g, aa_last, rd_prev)
+            aa_steps += aa_last is not None
+            if aa_last is not None:
+                # [reading] the inner dual warm start follows the extrapolated
+                # multipliers (multiplier identity lambda = -y)
+                y = -lam.copy()
+        rd_prev = rd
         x = x_new
         state = None
         if time.monotonic() > deadline:
@@ -801,10 +856,51 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
     res = Result(status=status, x=x_orig, lam=lam_out, outer_iters=k, counters=cnt,
                  gamma=gamma, lambda_hat=lam_hat, scaled_x=x, scaled_lam=lam_scaled_int,
                  sigma=sigma, omega=omega)
+    res.anderson_steps = aa_steps
     res.r_p, res.r_d, res.s_p, res.s_d = external_kkt(prob, x_orig, lam_out)
     Qo = sp.csr_matrix(prob["Q"])
     res.objective = 0.5 * float(x_orig @ (Qo @ x_orig)) + float(np.asarray(prob["c"]) @ x_orig)
     return res
+
+
+def _anderson_outer(st, S, me, u_form, lam, z, rp, rd, sp_, penalties_moved, aa_u, aa_g,
+                    aa_last, rd_prev):
+    """One outer step's Anderson bookkeeping.  [reading] The paper applies
+    the step once primal feasibility is reached and the row penalties are
+    stable, in the local convergence regime, and "when its safeguards hold",
+    without further detail.  Taken here:
+      * active when r_p meets the outer tolerance, no row penalty changed in
+        this step, and r_d decreased over this step (the plain outer map is
+        contracting; near a saddle the method moves away from the stationary
+        point, and extrapolation would pull it back); otherwise the history
+        is cleared;
+      * safeguard: when the outer residuals r_p or r_d grew since the last
+        extrapolation, the history is cleared (the next step is plain);
+      * the extrapolated lambda_I is projected onto lambda_I <= 0 and the
+        extrapolated centre onto the (scaled) box.
+    Returns the next (lambda, z) and the residuals recorded for the
+    safeguard."""
+    m = lam.shape[0]
+    if aa_last is not None and (rp > aa_last[0] or rd > aa_last[1]):
+        aa_u.clear()
+        aa_g.clear()
+    contracting = rd_prev is not None and rd < rd_prev
+    if not (rp <= st.eps_abs + st.eps_rel * sp_) or penalties_moved or not contracting:
+        aa_u.clear()
+        aa_g.clear()
+        return lam, z, None
+    aa_u.append(u_form)
+    aa_g.append(np.concatenate([lam, z]))
+    while len(aa_u) > st.anderson_mem + 1:
+        aa_u.pop(0)
+        aa_g.pop(0)
+    if len(aa_u) < 2:
+        return lam, z, None
+    v = anderson_step(aa_u, aa_g, st.anderson_reg)
+    lam_n = v[:m].copy()
+    lam_n[me:] = np.minimum(lam_n[me:], 0.0)
+    z_n = np.clip(v[m:], S.xl, S.xu)
+    return lam_n, z_n, (rp, rd)
 
 
 def external_kkt(prob, x, lam):

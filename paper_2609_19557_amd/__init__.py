@@ -5,6 +5,6 @@ that drive it.  The compute lives in ``libpdnqp.so`` (HIP); ``pdnqp`` is
 its Python binding."""
 
 from .pdnqp import (Solver, default_settings, load, solve_batch, PdnqpError,  # noqa: F401
-                    batch_report, batch_set_block, batch_autotune,
+                    batch_report, batch_set_config, batch_autotune, BATCH_CONFIGS,
                     SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR, STATUS_NAMES,
                     SCALE_RUIZ_A, SCALE_NONE, SCALE_RUIZ_QA, FP64, FP32)

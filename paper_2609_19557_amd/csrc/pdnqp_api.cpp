@@ -125,6 +125,8 @@ void pdnqp_default_settings(pdnqp_settings *s) {
   s->gamma_override = 0.0;
   s->step_boost = 1.0;
   s->outer_scaling = PDNQP_SCALE_RUIZ_A;
+  s->anderson_mem = 0;
+  s->anderson_reg = 1e-10;
 }
 
 size_t pdnqp_settings_size(void) { return sizeof(pdnqp_settings); }
@@ -150,7 +152,8 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         !(st.delta_gamma > 0) || !(st.step_boost > 0) || st.outer_scaling < 0 ||
         st.outer_scaling > 2 || st.trace_iters < 0 || st.trace_trials < 0 ||
         (st.precision != PDNQP_FP64 && st.precision != PDNQP_FP32) ||
-        (st.graph != 0 && st.graph != 1))
+        (st.graph != 0 && st.graph != 1) || st.anderson_mem < 0 ||
+        st.anderson_mem > PDNQP_ANDERSON_MAX || !(st.anderson_reg >= 0))
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);
@@ -326,16 +329,16 @@ int pdnqp_batch_last_report(pdnqp_batch_report *rep, double *done_ms, int32_t ca
   return PDNQP_OK;
 }
 
-int pdnqp_batch_set_block(int32_t block) {
+int pdnqp_batch_set_config(int32_t block, int32_t waves) {
   g_err.clear();
-  if (block != 0 && block != 256 && block != 512 && block != 1024)
-    return fail(PDNQP_E_INVALID, "block must be 0, 256, 512 or 1024");
-  pdnqp::set_batch_block(block);
+  if (pdnqp::set_batch_config(block, waves) != PDNQP_OK)
+    return fail(PDNQP_E_INVALID,
+                "configuration must be (256,1), (512,1), (1024,1), (256,4), (512,4) or block 0");
   return PDNQP_OK;
 }
 
 int pdnqp_batch_autotune(int32_t count, pdnqp_solver *const *solvers, int32_t probe_inner,
-                         int32_t *block_out, double *ms_out) {
+                         int32_t *block_out, int32_t *waves_out, double *ms_out) {
   g_err.clear();
   if (count < 1) return fail(PDNQP_E_INVALID, "count must be >= 1");
   if (probe_inner < 1) return fail(PDNQP_E_INVALID, "probe_inner must be >= 1");
@@ -344,7 +347,7 @@ int pdnqp_batch_autotune(int32_t count, pdnqp_solver *const *solvers, int32_t pr
   if (r) return r;
   req.probe_inner = probe_inner;
   std::string err;
-  r = pdnqp::autotune_batch(req, block_out, ms_out, err);
+  r = pdnqp::autotune_batch(req, block_out, waves_out, ms_out, err);
   if (r) return fail(r, err);
   return PDNQP_OK;
 }

@@ -39,8 +39,10 @@ struct BShared {
   double red[16][kRed];
   double res[kRed];
   double bc[4];
+  double aam[kAAMem][kAAMem + 1];  // Anderson Gram system (thread 0)
   uint64_t clock;
   int32_t inst;
+  int32_t aawin[kAAMem + 1];       // Anderson window: history slots, oldest first
 };
 
 // Check reduction slots (per candidate cd = 0 current, 1 average).
@@ -232,29 +234,44 @@ struct BSolver {
   // fin(row, acc) on one thread.  S is the staging type.  Ends with a
   // barrier, so fin's writes are visible to the whole workgroup afterwards.
   template <typename S, bool MAX, typename V, typename P, typename Fn>
-  __device__ __forceinline__ void rows(const BCsr &M, const V *val_, lp<S> stage, P &&entry, Fn &&fin) {
+  __device__ __forceinline__ void rows(const BCsr &M, const V *val_, lp<S> stage, P &&entry,
+                                       Fn &&fin) {
     const gp<const int32_t> rp = G(M.p);
     const gp<const int32_t> ci = G(M.i);
     const gp<const int32_t> rb = G(M.rb);
     const gp<const V> val = G(val_);
     const int nrb = uni(M.nrb);
-    for (int bk = 0; bk < nrb; ++bk) {
-      const int r0 = uni(rb[bk]), r1 = uni(rb[bk + 1]);
-      const int base = uni(rp[r0]);
-      const int cnt = uni(rp[r1]) - base;
-      if (cnt <= TILE) {
-        int col[E];
-        V vv[E];
+    if (nrb <= 0) return;
+    // the next tile's indices and values are loaded before the current tile
+    // is staged and summed, so their latency overlaps that work
+    int col[E], ncol[E];
+    V vv[E], nvv[E];
+    int r0 = uni(rb[0]), r1 = uni(rb[1]);
+    int base = uni(rp[r0]);
+    int cnt = uni(rp[r1]) - base;
+    auto load_tile = [&](int bs, int cn, int (&cc)[E], V (&vl)[E]) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int k = e * BT + threadIdx.x;
-          col[e] = 0;
-          vv[e] = V(0);
-          if (k < cnt) {
-            col[e] = __builtin_nontemporal_load(&ci[base + k]);
-            vv[e] = __builtin_nontemporal_load(&val[base + k]);
-          }
+      for (int e = 0; e < E; ++e) {
+        const int k = e * BT + threadIdx.x;
+        cc[e] = 0;
+        vl[e] = V(0);
+        if (k < cn) {
+          cc[e] = __builtin_nontemporal_load(&ci[bs + k]);
+          vl[e] = __builtin_nontemporal_load(&val[bs + k]);
         }
+      }
+    };
+    if (cnt <= TILE) load_tile(base, cnt, col, vv);
+    for (int bk = 0; bk < nrb; ++bk) {
+      int nr0 = 0, nr1 = 0, nbase = 0, ncnt = 0;
+      if (bk + 1 < nrb) {
+        nr0 = r1;
+        nr1 = uni(rb[bk + 2]);
+        nbase = uni(rp[nr0]);
+        ncnt = uni(rp[nr1]) - nbase;
+        if (ncnt <= TILE) load_tile(nbase, ncnt, ncol, nvv);
+      }
+      if (cnt <= TILE) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const int k = e * BT + threadIdx.x;
@@ -266,7 +283,7 @@ struct BSolver {
           const int a = rp[row] - base;
           const int b = rp[row + 1] - base;
           S acc = S(0);
-#pragma unroll 1
+#pragma unroll 4
           for (int k = a; k < b; ++k) acc = MAX ? vmax<S>(acc, stage[k]) : acc + stage[k];
           fin(row, acc);
         }
@@ -282,6 +299,15 @@ struct BSolver {
         allreduce<1>(vals, MAX ? 1u : 0u);
         if (threadIdx.x == 0) fin(r0, (S)vals[0]);
         __syncthreads();
+      }
+      r0 = nr0;
+      r1 = nr1;
+      base = nbase;
+      cnt = ncnt;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        col[e] = ncol[e];
+        vv[e] = nvv[e];
       }
     }
   }
@@ -1325,13 +1351,14 @@ struct BSolver {
     allreduce<8>(o, 0xFFu);
   }
 
-  // row penalties (penalty-trigger-eq)
-  __device__ __forceinline__ void penalties(bool have_prev, double rn, double gate_tol) {
+  // row penalties (penalty-trigger-eq); returns whether a penalty changed
+  __device__ __forceinline__ bool penalties(bool have_prev, double rn, double gate_tol) {
     const double theta = I.st.theta_sigma, growth = I.st.sigma_growth;
     const double sig_max = I.st.sigma_max;
     const int gate = uni(I.st.penalty_gate);
     const gp<double> sig = G(I.v.sigma), rprev = G(I.v.rprev);
     const gp<const double> rrow = G(I.v.rrow), lam = G(I.v.lam);
+    double moved[1] = {0.0};
     elems(m, [&](int j) {
       const double r = rrow[j];
       if (have_prev && rn > 0.0) {
@@ -1340,12 +1367,185 @@ struct BSolver {
         if (gate) trig = trig && (fabs(r) > gate_tol);
         if (trig) {
           const double fac = fmax(1.0, growth * fabs(r) / rn);
-          const double sn = sig[j] * fac;
-          sig[j] = sn < sig_max ? sn : sig_max;
+          const double so = sig[j];
+          const double sn = so * fac;
+          const double s2 = sn < sig_max ? sn : sig_max;
+          sig[j] = s2;
+          if (s2 != so) moved[0] = 1.0;
         }
       }
       rprev[j] = r;
     });
+    allreduce<1>(moved, 1u);
+    return moved[0] != 0.0;
+  }
+
+  // ---- Anderson acceleration of (lambda_E, lambda_I, z) (Section 3.2) ------
+  // Same readings as the oracle: active when r_p meets the tolerance, no
+  // penalty changed and r_d decreased; history cleared when the residuals
+  // grew after an extrapolation; lambda_I <= 0 and z in the box after it;
+  // the inner dual warm start follows (y = -lambda).
+  struct AAState {
+    int count;  // entries of the window sh.aawin
+    int form_slot;
+    bool last_valid;
+    double last_rp, last_rd;
+    int steps;
+  };
+
+  __device__ __forceinline__ int aa_win(int j) { return uni((int)sh.aawin[j]); }
+
+  __device__ __forceinline__ void aa_pack(double *dst_) {
+    const gp<double> dst = G(dst_);
+    const gp<const double> lam = G(I.v.lam), z = G(I.v.z);
+    elems(m + n, [&](int i) { dst[i] = i < m ? lam[i] : z[i - m]; });
+    __syncthreads();
+  }
+
+  __device__ __forceinline__ void aa_form(AAState &a) {
+    const int cap = uni(I.st.anderson_mem) + 2;
+    int slot = 0;
+    for (; slot < cap; ++slot) {
+      bool used = false;
+      for (int j = 0; j < a.count; ++j) used = used || (aa_win(j) == slot);
+      if (!used) break;
+    }
+    a.form_slot = slot;
+    aa_pack(I.AU + (size_t)slot * (n + m));
+  }
+
+  __device__ __forceinline__ void aa_step(AAState &a, double rp, double rd, double sp,
+                                          double rd_prev, bool moved) {
+    const int mem = uni(I.st.anderson_mem);
+    const size_t len = (size_t)n + m;
+    if (a.last_valid && (rp > a.last_rp || rd > a.last_rd)) a.count = 0;
+    a.last_valid = false;
+    const bool contracting = rd < rd_prev;
+    if (!(rp <= I.eps_abs + I.eps_rel * sp) || moved || !contracting) {
+      a.count = 0;
+      return;
+    }
+    aa_pack(I.AG + (size_t)a.form_slot * len);
+    // append the slot, dropping the oldest beyond mem + 1 entries
+    if (threadIdx.x == 0) {
+      int cnt = a.count;
+      sh.aawin[cnt++] = a.form_slot;
+      while (cnt > mem + 1) {
+        for (int j = 0; j + 1 < cnt; ++j) sh.aawin[j] = sh.aawin[j + 1];
+        cnt -= 1;
+      }
+    }
+    __syncthreads();
+    a.count = a.count + 1 > mem + 1 ? mem + 1 : a.count + 1;
+    if (a.count < 2) return;
+    const int p = a.count - 1;
+    const gp<const double> U = G((const double *)I.AU), Gh = G((const double *)I.AG);
+    const size_t op = (size_t)aa_win(p) * len;
+    // Gram of dF_j = f_{j+1} - f_j (f = G - U) and dF'f_p, one row per pass
+    for (int i = 0; i < p; ++i) {
+      double v[kAAMem + 1];
+#pragma unroll
+      for (int k = 0; k <= kAAMem; ++k) v[k] = 0.0;
+      const size_t oi0 = (size_t)aa_win(i) * len, oi1 = (size_t)aa_win(i + 1) * len;
+      size_t oj0[kAAMem], oj1[kAAMem];
+#pragma unroll
+      for (int j = 0; j < kAAMem; ++j) {
+        oj0[j] = j < p ? (size_t)aa_win(j) * len : 0;
+        oj1[j] = j < p ? (size_t)aa_win(j + 1) * len : 0;
+      }
+      elems((int)len, [&](int e) {
+        const double di = (Gh[oi1 + e] - U[oi1 + e]) - (Gh[oi0 + e] - U[oi0 + e]);
+#pragma unroll
+        for (int j = 0; j < kAAMem; ++j) {
+          if (j >= i && j < p) {
+            const double dj = (Gh[oj1[j] + e] - U[oj1[j] + e]) - (Gh[oj0[j] + e] - U[oj0[j] + e]);
+            v[j] += di * dj;
+          }
+        }
+        v[kAAMem] += di * (Gh[op + e] - U[op + e]);
+      });
+      allreduce<kAAMem + 1>(v, 0u);
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < kAAMem; ++j)
+          if (j >= i && j < p) sh.aam[i][j] = sh.aam[j][i] = v[j];
+        sh.aam[i][kAAMem] = v[kAAMem];
+      }
+    }
+    __syncthreads();
+    // thread 0 solves (partial pivoting; gamma = 0 if singular) and broadcasts
+    if (threadIdx.x == 0) {
+      double(*M)[kAAMem + 1] = sh.aam;
+      double tr = 0.0;
+      for (int i = 0; i < p; ++i) tr += M[i][i];
+      const double tik = I.st.anderson_reg * tr / p;
+      for (int i = 0; i < p; ++i) M[i][i] += tik;
+      bool singular = false;
+      for (int cc = 0; cc < p && !singular; ++cc) {
+        int piv = cc;
+        for (int i = cc + 1; i < p; ++i)
+          if (fabs(M[i][cc]) > fabs(M[piv][cc])) piv = i;
+        if (M[piv][cc] == 0.0) {
+          singular = true;
+          break;
+        }
+        if (piv != cc) {
+          for (int j = 0; j < p; ++j) {
+            const double t = M[cc][j];
+            M[cc][j] = M[piv][j];
+            M[piv][j] = t;
+          }
+          const double t = M[cc][kAAMem];
+          M[cc][kAAMem] = M[piv][kAAMem];
+          M[piv][kAAMem] = t;
+        }
+        for (int i = cc + 1; i < p; ++i) {
+          const double f = M[i][cc] / M[cc][cc];
+          for (int j = cc; j < p; ++j) M[i][j] -= f * M[cc][j];
+          M[i][kAAMem] -= f * M[cc][kAAMem];
+        }
+      }
+      for (int i = 0; i < kAAMem; ++i) sh.res[i] = 0.0;
+      if (!singular) {
+        for (int i = p - 1; i >= 0; --i) {
+          double acc = M[i][kAAMem];
+          for (int j = i + 1; j < p; ++j) acc -= M[i][j] * sh.res[j];
+          sh.res[i] = acc / M[i][i];
+        }
+      }
+    }
+    __syncthreads();
+    double gam[kAAMem];
+    size_t og[kAAMem + 1];
+#pragma unroll
+    for (int i = 0; i < kAAMem; ++i) gam[i] = uni(sh.res[i]);
+#pragma unroll
+    for (int j = 0; j <= kAAMem; ++j) og[j] = j <= p ? (size_t)aa_win(j) * len : 0;
+    __syncthreads();
+    // combination and projections; inner dual start y = -lambda
+    {
+      const gp<double> lam = G(I.v.lam), z = G(I.v.z), Y = G(I.v.Y[c.cur]);
+      const gp<const double> lo = G(I.lo), hi = G(I.hi);
+      elems((int)len, [&](int e) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < kAAMem; ++j)
+          if (j < p) acc += gam[j] * (Gh[og[j + 1] + e] - Gh[og[j] + e]);
+        const double v = Gh[og[p] + e] - acc;
+        if (e < m) {
+          const double l = (e >= me && v > 0.0) ? 0.0 : v;
+          lam[e] = l;
+          Y[e] = -l;
+        } else {
+          z[e - m] = clampv<double>(v, lo[e - m], hi[e - m]);
+        }
+      });
+    }
+    __syncthreads();
+    a.last_valid = true;
+    a.last_rp = rp;
+    a.last_rd = rd;
+    a.steps += 1;
   }
 
   // ---- the whole method ------------------------------------------------------
@@ -1372,8 +1572,19 @@ struct BSolver {
     int64_t k = 0;
     const int64_t max_outer = I.st.max_outer;
     double rp = NAN, rd = NAN, sp = NAN, sd = NAN;
+    const bool aa_on = uni(I.st.anderson_mem) > 0;
+    AAState aa;
+    aa.count = 0;
+    aa.form_slot = 0;
+    aa.last_valid = false;
+    aa.last_rp = aa.last_rd = 0.0;
+    aa.steps = 0;
+    double rd_prev = NAN;
     while (k < max_outer) {
-      if (need_form) form_inner(gamma);
+      if (need_form) {
+        if (aa_on) aa_form(aa);
+        form_inner(gamma);
+      }
       const int ist = run_inner(deadline);
       if constexpr (F32) {
         const int cur = c.cur;
@@ -1414,7 +1625,7 @@ struct BSolver {
         status = PDNQP_SOLVED;
         break;
       }
-      penalties(have_prev, rn, eps_abs + eps_rel * sp);
+      const bool moved = penalties(have_prev, rn, eps_abs + eps_rel * sp);
       have_prev = true;
       // inner tolerances (inner-tolerance-factor)
       const double ratio = (rd == 0.0) ? 1.0 : fmin(1.0, dxz / gamma / rd);
@@ -1434,6 +1645,8 @@ struct BSolver {
         }
       }
       __syncthreads();
+      if (aa_on) aa_step(aa, rp, rd, sp, rd_prev, moved);
+      rd_prev = rd;
       need_form = true;
       if (clock_now() > deadline) {
         status = PDNQP_TIME_LIMIT;
@@ -1460,6 +1673,7 @@ struct BSolver {
       o->trace_trials_n = c.trace_trials_n;
       o->trace_checks_n = c.trace_checks_n;
       o->staged = STAGE ? 1 : 0;
+      o->anderson_steps = aa_on ? aa.steps : 0;
       o->outer_iters = k;
       o->trials = c.trials;
       o->accepted = c.accepted;
@@ -1482,8 +1696,8 @@ struct BSolver {
   }
 };
 
-template <typename T, int BT>
-__global__ __launch_bounds__(BT) void k_batch(const BatchInst *__restrict__ insts,
+template <typename T, int BT, int WAVES>
+__global__ __launch_bounds__(BT, WAVES) void k_batch(const BatchInst *__restrict__ insts,
                                               const int32_t *__restrict__ order, int count,
                                               uint32_t *__restrict__ queue, int lds_bytes) {
   extern __shared__ double bsmem[];
@@ -1514,51 +1728,45 @@ __global__ __launch_bounds__(BT) void k_batch(const BatchInst *__restrict__ inst
 
 }  // namespace
 
-int batch_launch(hipStream_t st, int precision, int block, int grid, size_t lds_bytes,
+// Configurations: workgroup size, and the minimum waves per SIMD the
+// compiler must allow (1: its own register budget; 4: at most 128 VGPRs).
+#define PDNQP_BATCH_CONFIGS(X, TT) \
+  X(TT, 256, 1, 0)                 \
+  X(TT, 512, 1, 1)                 \
+  X(TT, 1024, 1, 2)                \
+  X(TT, 256, 4, 3)                 \
+  X(TT, 512, 4, 4)
+
+int batch_launch(hipStream_t st, int precision, int config, int grid, size_t lds_bytes,
                  const BatchInst *insts, const int32_t *order, int count, uint32_t *queue) {
   if (grid < 1 || count < 1) return PDNQP_OK;
   const int lb = (int)lds_bytes;
-#define PDNQP_BATCH_CASE(TT, BB)                                                           \
-  hipLaunchKernelGGL((k_batch<TT, BB>), dim3(grid), dim3(BB), lds_bytes, st, insts, order, \
-                     count, queue, lb)
+  bool found = false;
+#define PDNQP_BATCH_CASE(TT, BB, WW, ID)                                                       \
+  if (config == ID) {                                                                          \
+    hipLaunchKernelGGL((k_batch<TT, BB, WW>), dim3(grid), dim3(BB), lds_bytes, st, insts, order, \
+                       count, queue, lb);                                                      \
+    found = true;                                                                              \
+  }
   if (precision == PDNQP_FP32) {
-    switch (block) {
-      case 256: PDNQP_BATCH_CASE(float, 256); break;
-      case 512: PDNQP_BATCH_CASE(float, 512); break;
-      case 1024: PDNQP_BATCH_CASE(float, 1024); break;
-      default: return PDNQP_E_INVALID;
-    }
+    PDNQP_BATCH_CONFIGS(PDNQP_BATCH_CASE, float)
   } else {
-    switch (block) {
-      case 256: PDNQP_BATCH_CASE(double, 256); break;
-      case 512: PDNQP_BATCH_CASE(double, 512); break;
-      case 1024: PDNQP_BATCH_CASE(double, 1024); break;
-      default: return PDNQP_E_INVALID;
-    }
+    PDNQP_BATCH_CONFIGS(PDNQP_BATCH_CASE, double)
   }
 #undef PDNQP_BATCH_CASE
+  if (!found) return PDNQP_E_INVALID;
   return hipGetLastError() == hipSuccess ? PDNQP_OK : PDNQP_E_DEVICE;
 }
 
-int batch_occupancy(int precision, int block, size_t lds_bytes) {
+int batch_occupancy(int precision, int config, size_t lds_bytes) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
-#define PDNQP_BATCH_OCC(TT, BB) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<TT, BB>, BB, lds_bytes)
+#define PDNQP_BATCH_OCC(TT, BB, WW, ID) \
+  if (config == ID) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<TT, BB, WW>, BB, lds_bytes);
   if (precision == PDNQP_FP32) {
-    switch (block) {
-      case 256: PDNQP_BATCH_OCC(float, 256); break;
-      case 512: PDNQP_BATCH_OCC(float, 512); break;
-      case 1024: PDNQP_BATCH_OCC(float, 1024); break;
-      default: return 0;
-    }
+    PDNQP_BATCH_CONFIGS(PDNQP_BATCH_OCC, float)
   } else {
-    switch (block) {
-      case 256: PDNQP_BATCH_OCC(double, 256); break;
-      case 512: PDNQP_BATCH_OCC(double, 512); break;
-      case 1024: PDNQP_BATCH_OCC(double, 1024); break;
-      default: return 0;
-    }
+    PDNQP_BATCH_CONFIGS(PDNQP_BATCH_OCC, double)
   }
 #undef PDNQP_BATCH_OCC
   return e == hipSuccess ? nb : 0;

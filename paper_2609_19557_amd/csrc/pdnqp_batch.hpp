@@ -28,6 +28,8 @@ struct BatchOut {
   int32_t cur;
   int32_t trace_iters_n, trace_trials_n, trace_checks_n;
   int32_t staged;     // 1 when the gathered vectors were staged in LDS
+  int32_t anderson_steps;
+  int32_t pad;
   int64_t outer_iters, trials, accepted, rejected, restarts, checks;
   double rp, rd, sp, sd;  // scaled outer residuals and scales at exit
   double gamma, lam_hat, omega, c_obj;
@@ -50,6 +52,7 @@ struct BatchInst {
   Vecs v;
   double *Fx2, *Fs2, *Fr2, *E2buf;
   double *lz;  // Lanczos coefficients: alpha [0, k), beta [k, 2k)
+  double *AU, *AG;  // Anderson histories: (anderson_mem + 2) slots of (lambda, z)
   IterVecs<double> w64;
   IterVecs<float> w32;
   BatchOut *out;
@@ -67,15 +70,23 @@ __host__ __device__ inline size_t batch_lds_bytes(int block, int n, int m, int p
   return bytes;
 }
 
-// Supported workgroup sizes.
-constexpr int kBatchBlocks[] = {256, 512, 1024};
+// Launch configurations of the persistent kernel: workgroup size and the
+// minimum waves per SIMD given to the compiler (1: its own register budget,
+// 4: at most 128 VGPRs, more workgroups per CU, some spills).
+struct BatchConfig {
+  int block;
+  int waves;
+};
+constexpr BatchConfig kBatchConfigs[] = {{256, 1}, {512, 1}, {1024, 1}, {256, 4}, {512, 4}};
+constexpr int kBatchNumConfigs = 5;
 
-// Launches the persistent kernel over `count` instances taken in the order
-// `order` (device array); `queue` is a zeroed device counter.
-int batch_launch(hipStream_t st, int precision, int block, int grid, size_t lds_bytes,
+// Launches the persistent kernel (configuration index `config`) over
+// `count` instances taken in the order `order` (device array); `queue` is
+// a zeroed device counter.
+int batch_launch(hipStream_t st, int precision, int config, int grid, size_t lds_bytes,
                  const BatchInst *insts, const int32_t *order, int count, uint32_t *queue);
 
 // Resident workgroups per CU for a configuration (0 if it cannot launch).
-int batch_occupancy(int precision, int block, size_t lds_bytes);
+int batch_occupancy(int precision, int config, size_t lds_bytes);
 
 }  // namespace pdnqp

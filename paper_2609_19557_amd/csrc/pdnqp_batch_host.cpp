@@ -25,8 +25,14 @@ double now_s() {
 }
 
 std::mutex g_mu;
-std::map<std::tuple<int, int, int>, int> g_tuned;  // batch class -> workgroup size
-int g_forced_block = 0;
+std::map<std::tuple<int, int, int>, int> g_tuned;  // batch class -> configuration index
+int g_forced_config = -1;
+
+int config_index(int block, int waves) {
+  for (int i = 0; i < kBatchNumConfigs; ++i)
+    if (kBatchConfigs[i].block == block && kBatchConfigs[i].waves == waves) return i;
+  return -1;
+}
 
 int ilog2(double x) {
   int k = 0;
@@ -64,9 +70,16 @@ int hip_check(hipError_t e, const char *what, std::string &err) {
 
 }  // namespace
 
-void set_batch_block(int block) {
+int set_batch_config(int block, int waves) {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_forced_block = block;
+  if (block == 0) {
+    g_forced_config = -1;
+    return PDNQP_OK;
+  }
+  const int c = config_index(block, waves);
+  if (c < 0) return PDNQP_E_INVALID;
+  g_forced_config = c;
+  return PDNQP_OK;
 }
 
 int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<double> *done_ms,
@@ -91,27 +104,28 @@ int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<doub
   }
   int r;
   if ((r = hip_check(hipSetDevice(dev), "hipSetDevice", err))) return r;
-  // workgroup size
-  int block = req.block;
+  // launch configuration
+  int config = req.config;
   bool tuned = false;
-  if (!block) {
+  if (config < 0) {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_forced_block) {
-      block = g_forced_block;
+    if (g_forced_config >= 0) {
+      config = g_forced_config;
     } else {
       auto it = g_tuned.find(batch_class(S));
       if (it != g_tuned.end()) {
-        block = it->second;
+        config = it->second;
         tuned = true;
       } else {
-        block = 256;
+        config = 0;
       }
     }
   }
-  if (block != 256 && block != 512 && block != 1024) {
-    err = "batched solve: workgroup size must be 256, 512 or 1024";
+  if (config < 0 || config >= kBatchNumConfigs) {
+    err = "batched solve: unknown launch configuration";
     return PDNQP_E_INVALID;
   }
+  const int block = kBatchConfigs[config].block;
   hipDeviceProp_t prop;
   if ((r = hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties", err))) return r;
   int rate_khz = 0;
@@ -124,18 +138,25 @@ int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<doub
   }
   const double tps = 1000.0 * rate_khz;
   // dynamic LDS: the products' tile, plus staging for the largest instance
-  // that fits next to the workgroup's static LDS
-  const size_t lds_cap = prop.sharedMemPerBlock > 8192 ? prop.sharedMemPerBlock - 8192 : 0;
+  // that fits in this configuration's share of the CU's LDS (the register
+  // budget fixes how many workgroups share a CU)
   size_t lds = (size_t)batch_tile(block) * 8;
-  if (lds > lds_cap) {
-    err = "batched solve: not enough LDS per workgroup";
+  const int per_cu_regs = batch_occupancy(prec, config, lds);
+  if (per_cu_regs < 1) {
+    err = "batched solve: the kernel cannot be resident with this configuration";
     return PDNQP_E_DEVICE;
   }
+  const size_t cu_lds = prop.maxSharedMemoryPerMultiProcessor > 0
+                            ? (size_t)prop.maxSharedMemoryPerMultiProcessor
+                            : (size_t)prop.sharedMemPerBlock;
+  size_t lds_cap = cu_lds / per_cu_regs;
+  lds_cap = std::min(lds_cap, (size_t)prop.sharedMemPerBlock);
+  lds_cap = lds_cap > 8192 ? lds_cap - 8192 : 0;
   for (const Solver *s : S) {
     const size_t need = batch_lds_bytes(block, s->qp().n, s->qp().m, prec);
     if (need <= lds_cap) lds = std::max(lds, need);
   }
-  const int per_cu = batch_occupancy(prec, block, lds);
+  const int per_cu = batch_occupancy(prec, config, lds);
   if (per_cu < 1) {
     err = "batched solve: the kernel cannot be resident with this configuration";
     return PDNQP_E_DEVICE;
@@ -182,7 +203,7 @@ int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<doub
   hipEventCreate(&ev1);
   const double t_prep = now_s();
   hipEventRecord(ev0, st);
-  r = batch_launch(st, prec, block, grid, lds, (const BatchInst *)d_insts.p,
+  r = batch_launch(st, prec, config, grid, lds, (const BatchInst *)d_insts.p,
                    (const int32_t *)d_order.p, count, (uint32_t *)d_queue.p);
   hipEventRecord(ev1, st);
   hipError_t es = hipStreamSynchronize(st);
@@ -231,6 +252,7 @@ int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<doub
     for (int i = 0; i < count; ++i) (*done_ms)[i] = 1e3 * (double)(ho[i].t_end - first) / tps;
   }
   R.block = block;
+  R.waves = kBatchConfigs[config].waves;
   R.grid = grid;
   R.lds_bytes = (int32_t)lds;
   for (const BatchOut &o : ho) R.staged += o.staged;
@@ -243,34 +265,33 @@ int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<doub
   return PDNQP_OK;
 }
 
-int autotune_batch(const BatchRequest &req, int32_t *block_out, double *ms_out,
-                   std::string &err) {
+int autotune_batch(const BatchRequest &req, int32_t *block_out, int32_t *waves_out,
+                   double *ms_out, std::string &err) {
   if (req.solvers.empty()) {
     err = "autotune: empty batch";
     return PDNQP_E_INVALID;
   }
-  int best = 0;
+  int best = -1;
   double best_ms = 0.0;
-  int k = 0;
-  for (int block : kBatchBlocks) {
+  for (int c = 0; c < kBatchNumConfigs; ++c) {
     BatchRequest q = req;
-    q.block = block;
+    q.config = c;
     q.probe_inner = req.probe_inner > 0 ? req.probe_inner : 64;
     pdnqp_batch_report rep;
     const int r = run_batch(q, &rep, nullptr, err);
     if (r) return r;
-    if (ms_out) ms_out[k] = rep.kernel_ms;
-    if (!best || rep.kernel_ms < best_ms) {
-      best = block;
+    if (ms_out) ms_out[c] = rep.kernel_ms;
+    if (best < 0 || rep.kernel_ms < best_ms) {
+      best = c;
       best_ms = rep.kernel_ms;
     }
-    ++k;
   }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_tuned[batch_class(req.solvers)] = best;
   }
-  if (block_out) *block_out = best;
+  if (block_out) *block_out = kBatchConfigs[best].block;
+  if (waves_out) *waves_out = kBatchConfigs[best].waves;
   return PDNQP_OK;
 }
 

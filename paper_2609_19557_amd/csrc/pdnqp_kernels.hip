@@ -249,9 +249,11 @@ __global__ __launch_bounds__(kBlock) void k_outer_cols(Ctrl *__restrict__ c, Inn
 // its residual did not fall below theta times the previous one (equality
 // rows, and inequality rows with lambda < 0), by the factor
 // max(1, growth |r_i| / ||r||_inf), capped.
-__global__ __launch_bounds__(kBlock) void k_penalty(InnerParams p, Vecs v, int have_prev,
-                                                    double rnorm, double theta, double growth,
-                                                    double sig_max, int gate, double gate_tol) {
+__global__ __launch_bounds__(kBlock) void k_penalty(Ctrl *__restrict__ c, InnerParams p, Vecs v,
+                                                    int have_prev, double rnorm, double theta,
+                                                    double growth, double sig_max, int gate,
+                                                    double gate_tol) {
+  int moved = 0;
   for_elems(p.m, blockIdx.x, gridDim.x, [&](int j) {
     const double r = v.rrow[j];
     if (have_prev && rnorm > 0.0) {
@@ -260,12 +262,91 @@ __global__ __launch_bounds__(kBlock) void k_penalty(InnerParams p, Vecs v, int h
       if (gate) trig = trig && (fabs(r) > gate_tol);
       if (trig) {
         const double fac = fmax(1.0, growth * fabs(r) / rnorm);
-        const double sn = v.sigma[j] * fac;
-        v.sigma[j] = sn < sig_max ? sn : sig_max;
+        const double so = v.sigma[j];
+        const double sn = so * fac;
+        const double s2 = sn < sig_max ? sn : sig_max;
+        v.sigma[j] = s2;
+        moved |= (s2 != so);
       }
     }
     v.rprev[j] = r;
   });
+  if (moved) atomicOr(&c->pen_moved, 1);
+}
+
+// ===========================================================================
+// Anderson acceleration of the outer duals and the centre (Section 3.2,
+// "Anderson acceleration"): Type-II mixing over the stored points.
+// ===========================================================================
+__global__ __launch_bounds__(kBlock) void k_aa_pack(double *dst, const double *lam,
+                                                    const double *z, int32_t m, int32_t n) {
+  for_elems(m + n, blockIdx.x, gridDim.x, [&](int i) { dst[i] = i < m ? lam[i] : z[i - m]; });
+}
+
+// Gram matrix dF'dF (upper triangle, row by row) and dF'f_p of the residual
+// differences dF_j = f_{j+1} - f_j, f_j = G_j - U_j, over the points
+// slot[0..p]; per-block partials, fixed-order combination by the last block.
+__global__ __launch_bounds__(kBlock) void k_aa_gram(Ctrl *__restrict__ c, const double *U,
+                                                    const double *G, int64_t len, AASlots sl,
+                                                    int p, double *partial) {
+  double a[kAASums];
+#pragma unroll
+  for (int k = 0; k < kAASums; ++k) a[k] = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * kBlock) {
+    double f[kAAMem + 1];
+#pragma unroll
+    for (int j = 0; j <= kAAMem; ++j) {
+      f[j] = 0.0;
+      if (j <= p) {
+        const int64_t off = (int64_t)sl.s[j] * len + e;
+        f[j] = G[off] - U[off];
+      }
+    }
+    double d[kAAMem];
+#pragma unroll
+    for (int j = 0; j < kAAMem; ++j) d[j] = (j < p) ? f[j + 1] - f[j] : 0.0;
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < kAAMem; ++i) {
+#pragma unroll
+      for (int j = i; j < kAAMem; ++j) a[k++] += d[i] * d[j];
+    }
+    double fp = 0.0;
+#pragma unroll
+    for (int j = 0; j <= kAAMem; ++j)
+      if (j == p) fp = f[j];
+#pragma unroll
+    for (int i = 0; i < kAAMem; ++i) a[k++] += d[i] * fp;
+  }
+  block_reduce<kAASums>(a, 0u, partial, blockIdx.x);
+  if (last_block(&c->ticket[TK_AA], gridDim.x)) {
+    double r[kAASums];
+    final_reduce<kAASums>(partial, gridDim.x, 0u, r);
+    if (threadIdx.x == 0) {
+      for (int k = 0; k < kAASums; ++k) c->aa[k] = r[k];
+      c->ticket[TK_AA] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_aa_combine(const double *G, int64_t len, AASlots sl,
+                                                       int p, double *lam, double *z,
+                                                       const double *lo, const double *hi,
+                                                       int32_t me, int32_t m, int32_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * kBlock) {
+    double acc = 0.0;
+    for (int j = 0; j < p; ++j)
+      acc += sl.gamma[j] * (G[(int64_t)sl.s[j + 1] * len + e] - G[(int64_t)sl.s[j] * len + e]);
+    const double v = G[(int64_t)sl.s[p] * len + e] - acc;
+    if (e < m) {
+      lam[e] = (e >= me && v > 0.0) ? 0.0 : v;
+    } else {
+      const int i = (int)(e - m);
+      z[i] = clampv<double>(v, lo[i], hi[i]);
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy(double *dst, const double *src, int32_t n) {
@@ -549,12 +630,33 @@ void launch_outer_cols(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs
   (void)pq;
 }
 
-void launch_penalty(hipStream_t st, const InnerParams &p, const Vecs &v, const Part &pr,
-                    int have_prev, double rnorm, double theta, double growth, double sig_max,
-                    int gate, double gate_tol) {
+void launch_penalty(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
+                    const Part &pr, int have_prev, double rnorm, double theta, double growth,
+                    double sig_max, int gate, double gate_tol) {
   if (p.m == 0) return;
-  hipLaunchKernelGGL(k_penalty, dim3(nz(pr.blocks)), dim3(kBlock), 0, st, p, v, have_prev, rnorm,
-                     theta, growth, sig_max, gate, gate_tol);
+  hipLaunchKernelGGL(k_penalty, dim3(nz(pr.blocks)), dim3(kBlock), 0, st, c, p, v, have_prev,
+                     rnorm, theta, growth, sig_max, gate, gate_tol);
+}
+
+void launch_aa_pack(hipStream_t st, double *dst, const double *lam, const double *z, int32_t m,
+                    int32_t n) {
+  const int blocks = (int)std::min<int64_t>(((int64_t)m + n + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_aa_pack, dim3(nz(blocks)), dim3(kBlock), 0, st, dst, lam, z, m, n);
+}
+
+void launch_aa_gram(hipStream_t st, Ctrl *c, const double *U, const double *G, int64_t len,
+                    const AASlots &sl, int p, double *partial) {
+  const int blocks = (int)std::min<int64_t>((len + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_aa_gram, dim3(nz(blocks)), dim3(kBlock), 0, st, c, U, G, len, sl, p,
+                     partial);
+}
+
+void launch_aa_combine(hipStream_t st, const double *G, int64_t len, const AASlots &sl, int p,
+                       double *lam, double *z, const double *lo, const double *hi, int32_t me,
+                       int32_t m, int32_t n) {
+  const int blocks = (int)std::min<int64_t>((len + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_aa_combine, dim3(nz(blocks)), dim3(kBlock), 0, st, G, len, sl, p, lam, z,
+                     lo, hi, me, m, n);
 }
 
 void launch_copy(hipStream_t st, double *dst, const double *src, int32_t n) {

@@ -42,6 +42,7 @@ enum Ticket : int {
   TK_OUTER_COLS = 7,
   TK_GEN = 8,
   TK_APPLY = 9,
+  TK_AA = 10,
   TK_COUNT = 16
 };
 
@@ -77,7 +78,15 @@ struct Ctrl {
   double gen[8];       // general-purpose reductions (set-up)
   int64_t trials, accepted, rejected, restarts, checks;
   uint32_t ticket[TK_COUNT];
+  int32_t pen_moved;   // set by the penalty update when a row penalty changed
+  int32_t pad1;
+  double aa[48];       // Anderson Gram matrix (upper triangle) and right-hand side
 };
+
+// Anderson acceleration (outer duals and centre): at most kAAMem + 1 stored
+// points; the Gram system has at most kAAMem unknowns.
+constexpr int kAAMem = 8;
+constexpr int kAASums = kAAMem * (kAAMem + 1) / 2 + kAAMem;  // 44
 
 // Read-only parameters of one inner QP, passed by value.
 struct InnerParams {
@@ -147,7 +156,7 @@ struct Vecs {
   // set-up
   double *Dx, *Dc, *Ex, *Fx, *Fs, *Fr, *tmp_n, *tmp_m;
   // reductions
-  double *partial;                 // kMaxParts * 32 doubles
+  double *partial;                 // kMaxParts * 48 doubles
   // trace
   double *trace_w, *trace_y, *trace_tr;
   int32_t *trace_ck;
@@ -216,10 +225,25 @@ void launch_outer_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs
                        const Csr &A, const Part &pa);
 void launch_outer_cols(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
                        const Csr &Q, const Csr &AT, const Part &pq);
-void launch_penalty(hipStream_t st, const InnerParams &p, const Vecs &v, const Part &pr,
-                    int have_prev, double rnorm, double theta, double growth, double sig_max,
-                    int gate, double gate_tol);
+void launch_penalty(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
+                    const Part &pr, int have_prev, double rnorm, double theta, double growth,
+                    double sig_max, int gate, double gate_tol);
 void launch_copy(hipStream_t st, double *dst, const double *src, int32_t n);
+// Anderson: dst = (lam, z); Gram of the residual differences of the points
+// slot[0..p] (oldest first) of the histories U, G (row stride len);
+// combination G_p - sum gamma_j (G_{j+1} - G_j) into (lam, z) with
+// lam_I <= 0 and z in [lo, hi].
+void launch_aa_pack(hipStream_t st, double *dst, const double *lam, const double *z, int32_t m,
+                    int32_t n);
+struct AASlots {
+  int32_t s[kAAMem + 1];
+  double gamma[kAAMem];
+};
+void launch_aa_gram(hipStream_t st, Ctrl *c, const double *U, const double *G, int64_t len,
+                    const AASlots &sl, int p, double *partial);
+void launch_aa_combine(hipStream_t st, const double *G, int64_t len, const AASlots &sl, int p,
+                       double *lam, double *z, const double *lo, const double *hi, int32_t me,
+                       int32_t m, int32_t n);
 void launch_fill(hipStream_t st, double *dst, double val, int32_t n);
 
 // ---- set-up ----------------------------------------------------------------

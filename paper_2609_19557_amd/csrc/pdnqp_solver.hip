@@ -184,7 +184,12 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   v_.Dx = D(n); v_.Dc = D(m); v_.Ex = nullptr;
   v_.Fx = D(n); v_.Fs = D(mi); v_.Fr = D(m); v_.tmp_n = D(n); v_.tmp_m = D(m);
   Fx2_ = D(n); Fs2_ = D(mi); Fr2_ = D(m); E2buf_ = D(m);
-  v_.partial = D((size_t)kMaxParts * 32);
+  v_.partial = D((size_t)kMaxParts * 48);
+  if (st_.anderson_mem > 0) {
+    const size_t len = (size_t)n + m;
+    AU_ = D((size_t)(st_.anderson_mem + 2) * len);
+    AG_ = D((size_t)(st_.anderson_mem + 2) * len);
+  }
   fp32_ = st_.precision == PDNQP_FP32;
   if (fp32_) {
     auto F = [&](size_t count) -> float * {
@@ -706,6 +711,9 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   int r;
   std::vector<double> x0c, lam0i;
   if ((r = begin(x0, lam0, x0c, lam0i, err))) return r;
+  aa_win_.clear();
+  aa_last_valid_ = false;
+  aa_steps_ = 0;
   // control block
   Ctrl hc;
   std::memset(&hc, 0, sizeof(hc));
@@ -737,6 +745,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   ip_.mode_init = 0;
 
   double delta_a = 1.0, delta_r = 1.0, eps_ak = 1.0, eps_rk = 1.0;
+  double rd_prev = NAN;  // r_d of the previous outer step (none yet: not contracting)
   bool have_prev = false, need_form = true;
   int status = PDNQP_MAX_ITER;
   int64_t k = 0;
@@ -745,6 +754,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     ip_.delta_a = delta_a;
     ip_.delta_r = delta_r;
     if (need_form) {
+      if (st_.anderson_mem > 0) anderson_form();
       form_inner(gamma);
       graph_valid_ = false;  // the inner parameters of the chunk changed
       if ((r = read_ctrl(err))) return r;
@@ -806,7 +816,12 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       break;
     }
     // row penalties (penalty-trigger-eq)
-    launch_penalty(stream_, ip_, v_, pr_, have_prev ? 1 : 0, rn, st_.theta_sigma,
+    if (st_.anderson_mem > 0) {
+      hctrl_->pen_moved = 0;
+      hipMemcpyAsync(&ctrl_->pen_moved, &hctrl_->pen_moved, sizeof(int32_t),
+                     hipMemcpyHostToDevice, stream_);
+    }
+    launch_penalty(stream_, ctrl_, ip_, v_, pr_, have_prev ? 1 : 0, rn, st_.theta_sigma,
                    st_.sigma_growth, st_.sigma_max, st_.penalty_gate, eps_abs + eps_rel * sp);
     have_prev = true;
     // inner tolerances (inner-tolerance-factor)
@@ -824,6 +839,11 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
         eps_rk = std::max(eps_rk, eps_rel);
       }
     }
+    // Anderson step on (lambda_E, lambda_I, z), Section 3.2
+    if (st_.anderson_mem > 0 &&
+        (r = anderson(rp, rd, sp, eps_abs, eps_rel, rd_prev, err)))
+      return r;
+    rd_prev = rd;
     need_form = true;
     if (now_s() > deadline) {
       status = PDNQP_TIME_LIMIT;
@@ -854,6 +874,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   oc.trace_iters = hctrl_->trace_iters_n;
   oc.trace_trials = hctrl_->trace_trials_n;
   oc.trace_checks = hctrl_->trace_checks_n;
+  oc.anderson_steps = aa_steps_;
   if ((r = finish(oc, x_out, lam_out, info, err))) return r;
   if (info) info->solve_s = now_s() - t_start;
   return PDNQP_OK;
@@ -914,6 +935,7 @@ int Solver::finish(const Outcome &oc, double *x_out, double *lam_out, pdnqp_info
     info->lambda_hat = oc.lam_hat;
     info->omega = oc.omega;
     info->setup_s = oc.setup_s;
+    info->anderson_steps = oc.anderson_steps;
     external_check(xs, lam_orig, info);
   }
   return PDNQP_OK;
@@ -1076,6 +1098,8 @@ int Solver::batch_prepare(double eps_abs, double eps_rel, const double *x0, cons
   bi.Fr2 = Fr2_;
   bi.E2buf = E2buf_;
   bi.lz = lz_;
+  bi.AU = AU_;
+  bi.AG = AG_;
   bi.w64 = iv64();
   bi.w32 = iv32_;
   bi.out = dev_out;
@@ -1104,11 +1128,104 @@ int Solver::batch_finish(const BatchOut &o, double ticks_per_s, double *x_out, d
   oc.trace_iters = o.trace_iters_n;
   oc.trace_trials = o.trace_trials_n;
   oc.trace_checks = o.trace_checks_n;
+  oc.anderson_steps = o.anderson_steps;
   gamma_ = o.gamma;
   const int r = finish(oc, x_out, lam_out, info, err);
   if (r) return r;
   if (info) info->solve_s = (double)(o.t_end - o.t_begin) / ticks_per_s;
   return PDNQP_OK;
+}
+
+// ===========================================================================
+// Anderson acceleration of (lambda_E, lambda_I, z) (Section 3.2).  The
+// readings (activation, safeguard, projections, Tikhonov weight) are those
+// of the oracle; the Gram system is formed on the device and solved here.
+// ===========================================================================
+void Solver::anderson_form() {
+  const int cap = st_.anderson_mem + 2;
+  int slot = 0;
+  for (; slot < cap; ++slot)
+    if (std::find(aa_win_.begin(), aa_win_.end(), slot) == aa_win_.end()) break;
+  aa_form_slot_ = slot;
+  const int64_t len = (int64_t)qp_.n + qp_.m;
+  launch_aa_pack(stream_, AU_ + slot * len, v_.lam, v_.z, qp_.m, qp_.n);
+}
+
+int Solver::anderson(double rp, double rd, double sp, double eps_abs, double eps_rel,
+                     double rd_prev, std::string &err) {
+  const int32_t n = qp_.n, m = qp_.m;
+  const int64_t len = (int64_t)n + m;
+  int r = read_ctrl(err);  // penalty flag
+  if (r) return r;
+  const bool moved = hctrl_->pen_moved != 0;
+  if (aa_last_valid_ && (rp > aa_rp_ || rd > aa_rd_)) aa_win_.clear();
+  aa_last_valid_ = false;
+  // active: primal feasible, penalties unchanged, the plain map contracting
+  const bool contracting = rd < rd_prev;
+  if (!(rp <= eps_abs + eps_rel * sp) || moved || !contracting) {
+    aa_win_.clear();
+    return PDNQP_OK;
+  }
+  launch_aa_pack(stream_, AG_ + aa_form_slot_ * len, v_.lam, v_.z, m, n);
+  aa_win_.push_back(aa_form_slot_);
+  while ((int)aa_win_.size() > st_.anderson_mem + 1) aa_win_.erase(aa_win_.begin());
+  if (aa_win_.size() < 2) return PDNQP_OK;
+  const int p = (int)aa_win_.size() - 1;
+  AASlots sl{};
+  for (int j = 0; j <= p; ++j) sl.s[j] = aa_win_[j];
+  launch_aa_gram(stream_, ctrl_, AU_, AG_, len, sl, p, v_.partial);
+  if ((r = read_ctrl(err))) return r;
+  // unpack the upper triangle (kernel order) and the right-hand side
+  double M[kAAMem][kAAMem], rhs[kAAMem];
+  int k = 0;
+  for (int i = 0; i < kAAMem; ++i)
+    for (int j = i; j < kAAMem; ++j) {
+      M[i][j] = M[j][i] = hctrl_->aa[k];
+      ++k;
+    }
+  for (int i = 0; i < kAAMem; ++i) rhs[i] = hctrl_->aa[k++];
+  double tr = 0.0;
+  for (int i = 0; i < p; ++i) tr += M[i][i];
+  const double tik = st_.anderson_reg * tr / p;
+  for (int i = 0; i < p; ++i) M[i][i] += tik;
+  // Gaussian elimination with partial pivoting; an exactly singular system
+  // (all differences zero) gives gamma = 0, the plain point
+  double g[kAAMem] = {0.0};
+  bool singular = false;
+  for (int c = 0; c < p && !singular; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < p; ++i)
+      if (std::fabs(M[i][c]) > std::fabs(M[piv][c])) piv = i;
+    if (M[piv][c] == 0.0) {
+      singular = true;
+      break;
+    }
+    if (piv != c) {
+      for (int j = 0; j < p; ++j) std::swap(M[c][j], M[piv][j]);
+      std::swap(rhs[c], rhs[piv]);
+    }
+    for (int i = c + 1; i < p; ++i) {
+      const double f = M[i][c] / M[c][c];
+      for (int j = c; j < p; ++j) M[i][j] -= f * M[c][j];
+      rhs[i] -= f * rhs[c];
+    }
+  }
+  if (!singular) {
+    for (int i = p - 1; i >= 0; --i) {
+      double acc = rhs[i];
+      for (int j = i + 1; j < p; ++j) acc -= M[i][j] * g[j];
+      g[i] = acc / M[i][i];
+    }
+  }
+  for (int j = 0; j < p; ++j) sl.gamma[j] = g[j];
+  launch_aa_combine(stream_, AG_, len, sl, p, v_.lam, v_.z, lo_, hi_, qp_.me, m, n);
+  // the inner dual warm start follows the extrapolated multipliers (y = -lambda)
+  launch_elem(stream_, EL_NEG, v_.Y[hctrl_->cur], v_.lam, nullptr, 0.0, m);
+  aa_last_valid_ = true;
+  aa_rp_ = rp;
+  aa_rd_ = rd;
+  aa_steps_ += 1;
+  return check(hipGetLastError(), "anderson kernels", err);
 }
 
 }  // namespace pdnqp

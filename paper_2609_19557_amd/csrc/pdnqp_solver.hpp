@@ -48,6 +48,7 @@ struct Outcome {
   double rp = 0, rd = 0, sp = 0, sd = 0, gamma = 0, lam_hat = 0, omega = 0, c_obj = 1;
   double setup_s = 0;
   int32_t trace_iters = 0, trace_trials = 0, trace_checks = 0;
+  int32_t anderson_steps = 0;
 };
 
 class Solver {
@@ -162,6 +163,17 @@ class Solver {
   std::vector<BatchBlocks> bblocks_;
   double *lz_ = nullptr;
   int device_ = 0;
+  // Anderson acceleration: histories of points and images, (anderson_mem + 2)
+  // slots of (lambda, z) each; the window lists the slots in use, oldest first
+  double *AU_ = nullptr, *AG_ = nullptr;
+  std::vector<int> aa_win_;
+  int aa_form_slot_ = 0;
+  bool aa_last_valid_ = false;
+  double aa_rp_ = 0.0, aa_rd_ = 0.0;
+  int aa_steps_ = 0;
+  void anderson_form();
+  int anderson(double rp, double rd, double sp, double eps_abs, double eps_rel, double rd_prev,
+               std::string &err);
 };
 
 // Batched persistent solve over several handles (pdnqp_batch_host.cpp).
@@ -171,12 +183,13 @@ struct BatchRequest {
   double *const *x_out = nullptr;
   double *const *lam_out = nullptr;
   pdnqp_info *infos = nullptr;
-  int block = 0;        // 0: tuned or default
+  int config = -1;      // launch configuration index; -1: tuned or default
   int probe_inner = 0;  // > 0: tuning probe (one outer step, this many inner iterations)
 };
 int run_batch(const BatchRequest &req, pdnqp_batch_report *rep, std::vector<double> *done_ms,
               std::string &err);
-int autotune_batch(const BatchRequest &req, int32_t *block_out, double *ms_out, std::string &err);
-void set_batch_block(int block);
+int autotune_batch(const BatchRequest &req, int32_t *block_out, int32_t *waves_out,
+                   double *ms_out, std::string &err);
+int set_batch_config(int block, int waves);
 
 }  // namespace pdnqp

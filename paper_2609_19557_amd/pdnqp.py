@@ -65,6 +65,8 @@ class Settings(ctypes.Structure):
         ("center_floor", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("anderson_mem", ctypes.c_int32),
+        ("anderson_reg", ctypes.c_double),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),
@@ -75,7 +77,7 @@ class Settings(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("anderson_steps", ctypes.c_int32),
         ("outer_iters", ctypes.c_int64),
         ("inner_trials", ctypes.c_int64),
         ("inner_accepted", ctypes.c_int64),
@@ -99,7 +101,7 @@ class Info(ctypes.Structure):
     ]
 
     def as_dict(self):
-        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d = {name: getattr(self, name) for name, _ in self._fields_}
         d["status_name"] = STATUS_NAMES.get(self.status, str(self.status))
         return d
 
@@ -122,6 +124,8 @@ class BatchReport(ctypes.Structure):
         ("lds_bytes", ctypes.c_int32),
         ("staged", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
+        ("waves", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("kernel_ms", ctypes.c_double),
         ("prepare_s", ctypes.c_double),
         ("finish_s", ctypes.c_double),
@@ -132,7 +136,7 @@ class BatchReport(ctypes.Structure):
 EXPORTED = ["pdnqp_default_settings", "pdnqp_settings_size", "pdnqp_info_size", "pdnqp_create",
             "pdnqp_solve", "pdnqp_solve_batch", "pdnqp_destroy", "pdnqp_last_error",
             "pdnqp_dims", "pdnqp_get_trace", "pdnqp_kernel_stats", "pdnqp_batch_last_report",
-            "pdnqp_batch_set_block", "pdnqp_batch_autotune"]
+            "pdnqp_batch_set_config", "pdnqp_batch_autotune"]
 
 _lib = None
 
@@ -176,9 +180,9 @@ def load(path=None):
     lib.pdnqp_kernel_stats.restype = ctypes.c_int
     lib.pdnqp_batch_last_report.argtypes = [P(BatchReport), vp, i32]
     lib.pdnqp_batch_last_report.restype = ctypes.c_int
-    lib.pdnqp_batch_set_block.argtypes = [i32]
-    lib.pdnqp_batch_set_block.restype = ctypes.c_int
-    lib.pdnqp_batch_autotune.argtypes = [i32, P(vp), i32, P(i32), vp]
+    lib.pdnqp_batch_set_config.argtypes = [i32, i32]
+    lib.pdnqp_batch_set_config.restype = ctypes.c_int
+    lib.pdnqp_batch_autotune.argtypes = [i32, P(vp), i32, P(i32), P(i32), vp]
     lib.pdnqp_batch_autotune.restype = ctypes.c_int
     if lib.pdnqp_settings_size() != ctypes.sizeof(Settings):
         raise ImportError("pdnqp_settings layout mismatch between library and binding")
@@ -367,23 +371,29 @@ def batch_report(count=None):
     return d
 
 
-def batch_set_block(block):
-    """Workgroup size of later batched solves (256, 512, 1024; 0 = tuned)."""
+BATCH_CONFIGS = [(256, 1), (512, 1), (1024, 1), (256, 4), (512, 4)]
+
+
+def batch_set_config(block, waves=1):
+    """Launch configuration of later batched solves (see BATCH_CONFIGS);
+    block 0 returns to the autotuned choice."""
     lib = load()
-    code = lib.pdnqp_batch_set_block(int(block))
+    code = lib.pdnqp_batch_set_config(int(block), int(waves))
     if code != OK:
         raise _err(lib, code)
 
 
 def batch_autotune(solvers, probe_inner=64):
-    """Times each workgroup size on the batch (short probe) and caches the
-    fastest for the batch's class; returns (block, [ms for 256, 512, 1024])."""
+    """Times each launch configuration on the batch (short probe) and caches
+    the fastest for the batch's class; returns ((block, waves), [ms per
+    configuration in BATCH_CONFIGS order])."""
     lib = load()
     k = len(solvers)
     hs = (ctypes.c_void_p * k)(*[s.h.value for s in solvers])
-    blk = ctypes.c_int32()
-    ms = np.zeros(3)
-    code = lib.pdnqp_batch_autotune(k, hs, int(probe_inner), ctypes.byref(blk), _ptr(ms))
+    blk, wv = ctypes.c_int32(), ctypes.c_int32()
+    ms = np.zeros(len(BATCH_CONFIGS))
+    code = lib.pdnqp_batch_autotune(k, hs, int(probe_inner), ctypes.byref(blk), ctypes.byref(wv),
+                                    _ptr(ms))
     if code != OK:
         raise _err(lib, code)
-    return blk.value, ms.tolist()
+    return (blk.value, wv.value), ms.tolist()

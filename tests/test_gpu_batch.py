@@ -49,22 +49,22 @@ def parity_case():
     return probs, st, traces
 
 
-def _solve_batch(P, probs, st, block=0, **kw):
+def _solve_batch(P, probs, st, config=(0, 1), **kw):
     solvers = [P.Solver.from_problem(p, **_gpu_kwargs(st), **kw) for p in probs]
-    P.batch_set_block(block)
+    P.batch_set_config(*config)
     try:
         out = P.solve_batch(solvers, st.eps_abs, st.eps_rel)
     finally:
-        P.batch_set_block(0)
+        P.batch_set_config(0)
     return solvers, out, P.batch_report(len(probs))
 
 
-@pytest.mark.parametrize("block", [256, 512, 1024])
-def test_batch_fp64_iterates_match_oracle(P, parity_case, block):
+@pytest.mark.parametrize("config", [(256, 1), (512, 1), (1024, 1), (256, 4), (512, 4)])
+def test_batch_fp64_iterates_match_oracle(P, parity_case, config):
     probs, st, traces = parity_case
-    solvers, out, rep = _solve_batch(P, probs, st, block, trace_iters=ITERS,
+    solvers, out, rep = _solve_batch(P, probs, st, config, trace_iters=ITERS,
                                      trace_trials=4 * ITERS)
-    assert rep["block"] == block and rep["count"] == len(probs)
+    assert (rep["block"], rep["waves"]) == config and rep["count"] == len(probs)
     assert rep["staged"] == len(probs)  # small instances fit in LDS
     for k, (p, s, tr) in enumerate(zip(probs, solvers, traces)):
         t = s.trace()
@@ -90,7 +90,7 @@ def test_batch_fp64_unstaged_matches_oracle(P, parity_case):
     st = O.Settings(max_outer=2, max_inner=80, outer_scaling=2)
     tr = O.Trace(max_iters=60)
     O.solve(prob, st, trace=tr)
-    solvers, out, rep = _solve_batch(P, [prob], st, 256, trace_iters=60, trace_trials=200)
+    solvers, out, rep = _solve_batch(P, [prob], st, (256, 1), trace_iters=60, trace_trials=200)
     assert rep["staged"] == 0
     t = solvers[0].trace()
     assert_iterate_parity(tr, t, n_expect=60)
@@ -178,10 +178,27 @@ def test_batch_rejects_mixed_precision(P):
 def test_batch_autotune_caches_choice(P):
     probs = _batch(17, 8, 200, 2000)
     solvers = [P.Solver.from_problem(p, time_limit_s=60.0) for p in probs]
-    block, ms = P.batch_autotune(solvers, probe_inner=32)
-    assert block in (256, 512, 1024) and len(ms) == 3 and min(ms) > 0
-    assert ms[(256, 512, 1024).index(block)] == min(ms)
+    cfg, ms = P.batch_autotune(solvers, probe_inner=32)
+    assert cfg in P.BATCH_CONFIGS and len(ms) == 5 and min(ms) > 0
+    assert ms[P.BATCH_CONFIGS.index(cfg)] == min(ms)
     out = P.solve_batch(solvers)
     rep = P.batch_report(len(probs))
-    assert rep["tuned"] == 1 and rep["block"] == block
+    assert rep["tuned"] == 1 and (rep["block"], rep["waves"]) == cfg
     assert all(np.all(np.isfinite(x)) for x, _, _ in out)
+
+
+def test_batch_anderson_matches_oracle(P):
+    """Anderson acceleration inside the batched kernel: the same instance as
+    the single-solve Anderson test, next to two others in one launch; the
+    iterates before and after the first extrapolation match the oracle's."""
+    probs = [qpgen.random_indefinite_qp(300, 150, 5, 4, 1, instance=1)] + _batch(23, 2, 200, 400)
+    st = O.Settings(anderson_mem=5, outer_scaling=2, max_outer=400, eps_abs=1e-2, eps_rel=1e-2)
+    solvers, out, rep = _solve_batch(P, probs, st, trace_iters=1800, trace_trials=8000)
+    tr = O.Trace(max_iters=1800)
+    res_o = O.solve(probs[0], st, trace=tr)
+    assert res_o.anderson_steps >= 1
+    assert_iterate_parity(tr, solvers[0].trace(), n_expect=1800)
+    assert out[0][2]["anderson_steps"] >= 1
+    assert out[0][2]["status"] == res_o.status == O.SOLVED
+    for p, (x, lam, info) in zip(probs[1:], out[1:]):
+        assert info["status"] == O.solve(p, st).status

@@ -40,7 +40,7 @@ def _gpu_kwargs(st: O.Settings):
             "rho_in_max", "rho_z", "check_every", "max_rejects", "restart_suff", "restart_nec",
             "restart_art", "shrink_safety", "shrink_min", "shrink_max", "omega0", "sigma_growth",
             "sigma_max", "sigma0_min", "sigma0_max", "lanczos_iters", "gamma_override",
-            "step_boost", "outer_scaling"]
+            "step_boost", "outer_scaling", "anderson_mem", "anderson_reg"]
     kw = {k: getattr(st, k) for k in keys}
     kw["max_outer"] = int(min(st.max_outer, 2**62))
     kw["penalty_gate"] = int(st.penalty_gate)
@@ -284,3 +284,34 @@ def test_graph_replay_matches_stream_launches(P, precision):
     for key in ("w", "y", "trials", "checks"):
         assert np.array_equal(t0[key], t1[key]), key
     assert np.array_equal(x0, x1) and np.array_equal(l0, l1)
+
+
+def test_anderson_steps_match_oracle(P):
+    """Anderson acceleration of (lambda_E, lambda_I, z) (Section 3.2): on an
+    instance whose first extrapolation comes after 1600 accepted inner
+    iterations, the iterates before and after it match the oracle's at 1e-9
+    (the extrapolated multipliers and centre enter every later iterate)."""
+    prob = qpgen.random_indefinite_qp(300, 150, 5, 4, 1, instance=1)
+    st = _oracle_settings(anderson_mem=5, outer_scaling=2, max_outer=400, eps_abs=1e-2,
+                          eps_rel=1e-2)
+    first = []
+    tr = O.Trace(max_iters=1800)
+    orig = O._anderson_outer
+
+    def spy(*a, **k):
+        out = orig(*a, **k)
+        if out[2] is not None and not first:
+            first.append(len(tr.w))
+        return out
+
+    O._anderson_outer = spy
+    try:
+        res_o = O.solve(prob, st, trace=tr)
+    finally:
+        O._anderson_outer = orig
+    assert first and first[0] < 1700, "the oracle extrapolates inside the window"
+    s = P.Solver.from_problem(prob, trace_iters=1800, trace_trials=8000, **_gpu_kwargs(st))
+    x, lam, info = s.solve(st.eps_abs, st.eps_rel)
+    assert_iterate_parity(tr, s.trace(), n_expect=1800)
+    assert info["anderson_steps"] >= 1
+    assert info["status"] == res_o.status == O.SOLVED

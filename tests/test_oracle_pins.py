@@ -386,3 +386,68 @@ def test_mutation_penalty_block_dropped(monkeypatch):
         return qp
     monkeypatch.setattr(O, "form_inner_qp", bad_form)
     assert not _inner_matches_bruteforce(3)
+
+
+# ---------------------------------------------------------------------------
+# Anderson acceleration (Section 3.2, "Anderson acceleration")
+# ---------------------------------------------------------------------------
+
+def test_anderson_single_point_is_plain_iteration():
+    g = np.array([1.0, -2.0, 3.0])
+    assert np.array_equal(O.anderson_step([np.zeros(3)], [g], 0.0), g)
+
+
+def test_anderson_matches_constrained_form():
+    """The difference form equals the classical constrained form of Type-II
+    Anderson mixing: alpha = argmin ||sum_j alpha_j f_j||_2 subject to
+    sum_j alpha_j = 1, next point = sum_j alpha_j G_j."""
+    rng = np.random.default_rng(21)
+    U = [rng.normal(size=7) for _ in range(4)]
+    G = [rng.normal(size=7) for _ in range(4)]
+    v1 = O.anderson_step(U, G, 0.0)
+    F = np.column_stack([G[j] - U[j] for j in range(4)])
+    K = np.zeros((5, 5))
+    K[:4, :4] = 2.0 * F.T @ F
+    K[:4, 4] = 1.0
+    K[4, :4] = 1.0
+    rhs = np.zeros(5)
+    rhs[4] = 1.0
+    alpha = np.linalg.solve(K, rhs)[:4]
+    v2 = sum(alpha[j] * G[j] for j in range(4))
+    np.testing.assert_allclose(v1, v2, rtol=1e-10, atol=1e-12)
+
+
+def test_anderson_affine_map_finite_termination():
+    """On an affine contraction u -> M u + b in R^d, Type-II Anderson with
+    memory >= d reaches the fixed point (I - M)^{-1} b after d + 1 map
+    evaluations: its iterates are those of GMRES on (I - M) u = b, which
+    terminates in at most d steps."""
+    rng = np.random.default_rng(5)
+    d = 4
+    M = rng.normal(size=(d, d))
+    M *= 0.5 / np.abs(np.linalg.eigvals(M)).max()
+    b = rng.normal(size=d)
+    ustar = np.linalg.solve(np.eye(d) - M, b)
+    U, G = [], []
+    u = np.zeros(d)
+    for _ in range(d + 1):
+        U.append(u)
+        G.append(M @ u + b)
+        u = O.anderson_step(U, G, 0.0)
+    assert np.abs(u - ustar).max() <= 1e-9 * max(1.0, np.abs(ustar).max())
+    # the plain iteration is still far away after as many steps
+    v = np.zeros(d)
+    for _ in range(d + 1):
+        v = M @ v + b
+    assert np.abs(v - ustar).max() > 1e-3
+
+
+def test_anderson_in_solve_keeps_termination():
+    """With the paper's memory m_A = 5 the method still ends at a point that
+    meets the outer test, and the extrapolation is actually used."""
+    prob = qpgen.random_indefinite_qp(300, 150, 5, 4, 3, instance=1)
+    st = O.Settings(anderson_mem=5, outer_scaling=2, max_outer=3000)
+    res = O.solve(prob, st)
+    assert res.status == O.SOLVED
+    assert O.passes_external(res, 1e-3, 1e-3)
+    assert res.anderson_steps > 0
