@@ -119,6 +119,13 @@ typedef struct pdnqp_settings {
                               0 (default): off; at most PDNQP_ANDERSON_MAX */
   double anderson_reg;     /* [reading] Tikhonov weight of the Anderson least-squares problem,
                               relative to the mean diagonal of its Gram matrix; 1e-10 */
+  int32_t controller;      /* 0 (default): the adaptive inner-tolerance rule (inner-tolerance-factor);
+                              1: the learned controller loaded by pdnqp_set_controller sets the
+                              next inner tolerance, inner iteration budget and primal weight,
+                              falling back to the adaptive rule after 3 outer steps without
+                              progress of the outer KKT measure */
+  int32_t outer_log;       /* record the controller features of the first N outer steps
+                              (pdnqp_get_outer_log); 0 (default): none */
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */
@@ -150,6 +157,8 @@ typedef struct pdnqp_info {
   double omega;            /* final primal weight */
   double setup_s;          /* seconds in scaling/Lanczos/penalty set-up inside pdnqp_solve */
   double solve_s;          /* seconds of the whole pdnqp_solve call */
+  int32_t controller_fallback;  /* 1 if the learned controller handed over to the adaptive rule */
+  int32_t outer_logged;    /* outer steps recorded for pdnqp_get_outer_log */
 } pdnqp_info;
 
 /* Writes the defaults into *s.  Never fails. */
@@ -259,6 +268,45 @@ int pdnqp_batch_set_config(int32_t block, int32_t waves);
  * configuration in the order listed above. */
 int pdnqp_batch_autotune(int32_t count, pdnqp_solver *const *solvers, int32_t probe_inner,
                          int32_t *block_out, int32_t *waves_out, double *ms_out);
+
+/* ---- Learned outer-step controller --------------------------------------
+ * A fully connected network 16 -> 64 -> 64 -> 3 (ReLU after the hidden
+ * layers, FP32) maps the features of an outer step to the log of the next
+ * inner tolerance, the log of the next inner iteration budget and the log of
+ * the next primal weight.  Parameters: PDNQP_MLP_PARAMS floats, in the order
+ * W1 (16x64, input index major), b1 (64), W2 (64x64), b2 (64), W3 (64x3),
+ * b3 (3).  All arrays are caller-owned host buffers; the network runs on the
+ * current device. */
+enum { PDNQP_MLP_PARAMS = 5443, PDNQP_FEATURES = 16, PDNQP_OUTER_RECORD = 8 };
+
+/* y (count x 3) = network(theta, x (count x 16)). */
+int pdnqp_mlp_forward(const float *theta, const float *x, int32_t count, float *y);
+
+/* Gradient (PDNQP_MLP_PARAMS floats) and value of the mean squared error
+ * (1 / (3 count)) sum (network(x) - y)^2 over the batch. */
+int pdnqp_mlp_gradient(const float *theta, const float *x, const float *y, int32_t count,
+                       float *grad, double *loss);
+
+/* Adam (step lr, moments 0.9 / 0.999) on that loss over `epochs` passes of
+ * shuffled minibatches of `batch` samples (seeded); theta is updated in
+ * place; loss_curve (optional, `epochs` entries) gets the full-batch loss
+ * after each pass. */
+int pdnqp_mlp_train(float *theta, const float *x, const float *y, int32_t count, int32_t epochs,
+                    int32_t batch, float lr, uint64_t seed, float *loss_curve);
+
+/* Copies the controller parameters into the handle (used when
+ * settings.controller = 1). */
+int pdnqp_set_controller(pdnqp_solver *s, const float *theta);
+
+/* Outer steps recorded by the last pdnqp_solve (settings.outer_log): for
+ * each, the 16 controller features (log10 of r_p, r_d, s_p, s_d,
+ * ||x - z||_inf / gamma, delta_a, eps_a,k, omega, min / mean / max sigma,
+ * r_p / r_p,prev, r_d / r_d,prev, and of 1 + the step's accepted inner
+ * iterations, 1 + its restarts, 1 + k) and PDNQP_OUTER_RECORD raw values
+ * (r_p, r_d, s_p, s_d, omega at the end of the inner solve, its accepted
+ * inner iterations, its restarts, the inner tolerance delta_a it used).
+ * NULL buffers query the count. */
+int pdnqp_get_outer_log(const pdnqp_solver *s, int32_t *steps, double *features, double *record);
 
 /* Releases the handle and its device memory.  NULL is a no-op. */
 void pdnqp_destroy(pdnqp_solver *s);

@@ -153,7 +153,8 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         st.outer_scaling > 2 || st.trace_iters < 0 || st.trace_trials < 0 ||
         (st.precision != PDNQP_FP64 && st.precision != PDNQP_FP32) ||
         (st.graph != 0 && st.graph != 1) || st.anderson_mem < 0 ||
-        st.anderson_mem > PDNQP_ANDERSON_MAX || !(st.anderson_reg >= 0))
+        st.anderson_mem > PDNQP_ANDERSON_MAX || !(st.anderson_reg >= 0) ||
+        (st.controller != 0 && st.controller != 1) || st.outer_log < 0)
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);
@@ -350,6 +351,48 @@ int pdnqp_batch_autotune(int32_t count, pdnqp_solver *const *solvers, int32_t pr
   r = pdnqp::autotune_batch(req, block_out, waves_out, ms_out, err);
   if (r) return fail(r, err);
   return PDNQP_OK;
+}
+
+int pdnqp_mlp_forward(const float *theta, const float *x, int32_t count, float *y) {
+  g_err.clear();
+  if (count < 1 || !theta || !x || !y) return fail(PDNQP_E_INVALID, "invalid network arguments");
+  std::string err;
+  const int r = pdnqp::mlp_forward(theta, x, count, y, err);
+  return r ? fail(r, err) : PDNQP_OK;
+}
+
+int pdnqp_mlp_gradient(const float *theta, const float *x, const float *y, int32_t count,
+                       float *grad, double *loss) {
+  g_err.clear();
+  if (count < 1 || !theta || !x || !y || !grad)
+    return fail(PDNQP_E_INVALID, "invalid network arguments");
+  std::string err;
+  const int r = pdnqp::mlp_gradient(theta, x, y, count, grad, loss, err);
+  return r ? fail(r, err) : PDNQP_OK;
+}
+
+int pdnqp_mlp_train(float *theta, const float *x, const float *y, int32_t count, int32_t epochs,
+                    int32_t batch, float lr, uint64_t seed, float *loss_curve) {
+  g_err.clear();
+  if (count < 1 || epochs < 0 || batch < 1 || !(lr > 0) || !theta || !x || !y)
+    return fail(PDNQP_E_INVALID, "invalid training arguments");
+  std::string err;
+  const int r = pdnqp::mlp_train(theta, x, y, count, epochs, batch, lr, seed, loss_curve, err);
+  return r ? fail(r, err) : PDNQP_OK;
+}
+
+int pdnqp_set_controller(pdnqp_solver *s, const float *theta) {
+  g_err.clear();
+  if (!s || !theta) return fail(PDNQP_E_INVALID, "solver or parameters NULL");
+  std::string err;
+  const int r = s->s.set_controller(theta, err);
+  return r ? fail(r, err) : PDNQP_OK;
+}
+
+int pdnqp_get_outer_log(const pdnqp_solver *s, int32_t *steps, double *features, double *record) {
+  g_err.clear();
+  if (!s) return fail(PDNQP_E_INVALID, "solver is NULL");
+  return s->s.outer_log(steps, features, record);
 }
 
 void pdnqp_destroy(pdnqp_solver *s) { delete s; }

@@ -791,6 +791,10 @@ struct BSolver {
   }
 
   // ---- one trial step (pdqp-trial) and its acceptance test -------------------
+  // Elementwise passes load U consecutive-stride elements per thread before
+  // using any, so each pass pays a few memory round trips, not one per element.
+  static constexpr int U = F32 ? 4 : 2;
+
   __device__ __forceinline__ void trial() {
     const IterVecs<T> &w = iv();
     const int cur = c.cur, nxt = cur ^ 1;
@@ -809,25 +813,38 @@ struct BSolver {
                         tbx = G(w.taub_x), lo = G(w.lo), hi = G(w.hi);
       const gp<T> xt = G(w.X[nxt]), xbar = G(w.xbar), qxbar = G(w.qxbar);
       const lp<T> sx = lx;
-      elems(n, [&](int i) {
-        const T xi = x[i], qxi = qx[i];
-        T xbu = xbar[i], qbu = qxbar[i];
-        if (pend) {
-          xbu = (T(1) - ap) * xbu + ap * xi;
-          qbu = (T(1) - ap) * qbu + ap * qxi;
-          xbar[i] = xbu;
-          qxbar[i] = qbu;
+      for (int i0 = threadIdx.x; i0 < n; i0 += U * BT) {
+        T xi[U], qxi[U], xb[U], qb[U], ay[U], qv[U], tb[U], l[U], h[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * BT;
+          if (i < n) {
+            xi[u] = x[i]; qxi[u] = qx[i]; xb[u] = xbar[i]; qb[u] = qxbar[i]; ay[u] = aty[i];
+            qv[u] = ql[i]; tb[u] = tbx[i]; l[u] = lo[i]; h[u] = hi[i];
+          }
         }
-        const T tb = tbx[i];
-        const T hx = qxi + gi * xi;
-        const T hb = qbu + gi * xbu;
-        const T g = ql[i] + (T(1) - alpha) * hb + alpha * hx - aty[i];
-        const T xn = clampv<T>(xi - (sct * tb) * g, lo[i], hi[i]);
-        xt[i] = xn;
-        if constexpr (STAGE) sx[i] = xn;
-        const double d = (double)xn - (double)xi;
-        sums[0] += d * d / (double)tb;
-      });
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * BT;
+          if (i < n) {
+            T xbu = xb[u], qbu = qb[u];
+            if (pend) {
+              xbu = (T(1) - ap) * xbu + ap * xi[u];
+              qbu = (T(1) - ap) * qbu + ap * qxi[u];
+              xbar[i] = xbu;
+              qxbar[i] = qbu;
+            }
+            const T hx = qxi[u] + gi * xi[u];
+            const T hb = qbu + gi * xbu;
+            const T g = qv[u] + (T(1) - alpha) * hb + alpha * hx - ay[u];
+            const T xn = clampv<T>(xi[u] - (sct * tb[u]) * g, l[u], h[u]);
+            xt[i] = xn;
+            if constexpr (STAGE) sx[i] = xn;
+            const double d = (double)xn - (double)xi[u];
+            sums[0] += d * d / (double)tb[u];
+          }
+        }
+      }
     }
     __syncthreads();
     // Q x_tr = Q_off x_tr + diag(Q) x_tr
@@ -842,69 +859,86 @@ struct BSolver {
       rows<T, false>(I.Qo, qo_vals(), prodT, [&](int col, T a) { return a * xat(col); },
                      [&](int i, T s) { QXn[i] = s + qd[i] * xat(i); });
     }
-    // A x_tr and the row-local part of the trial
+    // A x_tr, parked (in LDS when staged, else in the check buffer A x_bar,
+    // which is free between checks); then the row-local part of the trial
     {
       const gp<const T> xtg = G(w.X[nxt]);
       const lp<T> sx = lx;
       const lp<T> sy = ly;
+      const gp<T> axp = G(w.axbar);
       auto xat = [&](int col) -> T {
         if constexpr (STAGE) return sx[col];
         else return xtg[col];
       };
+      rows<T, false>(I.A, a_vals(), prodT, [&](int col, T a) { return a * xat(col); },
+                     [&](int j, T ax) {
+                       if constexpr (STAGE) sy[j] = ax;
+                       else axp[j] = ax;
+                     });
       const gp<const T> Yc = G(w.Y[cur]), BWc = G(w.BW[cur]), Rc = G(w.R[cur]), sig = G(w.sigma),
                         lam = G(w.lam), b = G(w.b), tbr_ = G(w.taub_r), Sc = G(w.S[cur]),
                         tbs_ = G(w.taub_s), etab = G(w.etab);
       const gp<T> ybar = G(w.ybar), rbar = G(w.rbar), sbar = G(w.sbar), Sn = G(w.S[nxt]),
                   Rn = G(w.R[nxt]), BWn = G(w.BW[nxt]), Yn = G(w.Y[nxt]);
-      rows<T, false>(I.A, a_vals(), prodT, [&](int col, T a) { return a * xat(col); },
-                     [&](int j, T ax) {
-                       const T y = Yc[j];
-                       const T bw = BWc[j];
-                       const T r = Rc[j];
-                       const T sg = sig[j];
-                       const T lm = lam[j];
-                       const T bj = b[j];
-                       T rb_ = rbar[j];
-                       if (pend) {
-                         ybar[j] = (T(1) - ap) * ybar[j] + ap * y;
-                         rb_ = (T(1) - ap) * rb_ + ap * r;
-                         rbar[j] = rb_;
-                       }
-                       const T gr = (T(1) - alpha) * (sg * rb_) + alpha * (sg * r) + lm + y;
-                       const T tbr = tbr_[j];
-                       const T rt = r - (sct * tbr) * gr;
-                       T bwt, hj;
-                       double ds = 0.0, ds2t = 0.0;
-                       if (j < me) {
-                         bwt = ax - rt;
-                         hj = bj;
-                       } else {
-                         const int k = j - me;
-                         const T sv = Sc[k];
-                         if (pend) sbar[k] = (T(1) - ap) * sbar[k] + ap * sv;
-                         const T tbs = tbs_[k];
-                         const T st = maxv<T>(sv - (sct * tbs) * y, bj);
-                         Sn[k] = st;
-                         bwt = ax - st - rt;
-                         hj = T(0);
-                         ds = (double)st - (double)sv;
-                         ds2t = ds * ds / (double)tbs;
-                       }
-                       const T eb = etab[j];
-                       const T yt = y + (scy * eb) * (hj - bwt - beta * (bwt - bw));
-                       Rn[j] = rt;
-                       BWn[j] = bwt;
-                       Yn[j] = yt;
-                       if constexpr (STAGE) sy[j] = yt;
-                       const double dr = (double)rt - (double)r;
-                       const double dy = (double)yt - (double)y;
-                       sums[1] += dr * dr / (double)tbr + ds2t;
-                       sums[2] += dy * dy / (double)eb;
-                       sums[3] += fabs(dr * ((double)sg * dr));
-                       sums[4] += fabs(dr * dy) + fabs(ds * dy);
-                     });
+      for (int j0 = threadIdx.x; j0 < m; j0 += U * BT) {
+        T axv[U], y[U], bw[U], r[U], sg[U], lm[U], bj[U], rbv[U], tbr[U], eb[U], yb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int j = j0 + u * BT;
+          if (j < m) {
+            if constexpr (STAGE) axv[u] = sy[j];
+            else axv[u] = axp[j];
+            y[u] = Yc[j]; bw[u] = BWc[j]; r[u] = Rc[j]; sg[u] = sig[j]; lm[u] = lam[j];
+            bj[u] = b[j]; rbv[u] = rbar[j]; tbr[u] = tbr_[j]; eb[u] = etab[j];
+            yb[u] = pend ? ybar[j] : T(0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int j = j0 + u * BT;
+          if (j < m) {
+            T rb_ = rbv[u];
+            if (pend) {
+              ybar[j] = (T(1) - ap) * yb[u] + ap * y[u];
+              rb_ = (T(1) - ap) * rb_ + ap * r[u];
+              rbar[j] = rb_;
+            }
+            const T gr = (T(1) - alpha) * (sg[u] * rb_) + alpha * (sg[u] * r[u]) + lm[u] + y[u];
+            const T rt = r[u] - (sct * tbr[u]) * gr;
+            T bwt, hj;
+            double ds = 0.0, ds2t = 0.0;
+            if (j < me) {
+              bwt = axv[u] - rt;
+              hj = bj[u];
+            } else {
+              const int k = j - me;
+              const T sv = Sc[k];
+              if (pend) sbar[k] = (T(1) - ap) * sbar[k] + ap * sv;
+              const T tbs = tbs_[k];
+              const T st = maxv<T>(sv - (sct * tbs) * y[u], bj[u]);
+              Sn[k] = st;
+              bwt = axv[u] - st - rt;
+              hj = T(0);
+              ds = (double)st - (double)sv;
+              ds2t = ds * ds / (double)tbs;
+            }
+            const T yt = y[u] + (scy * eb[u]) * (hj - bwt - beta * (bwt - bw[u]));
+            Rn[j] = rt;
+            BWn[j] = bwt;
+            Yn[j] = yt;
+            if constexpr (STAGE) sy[j] = yt;
+            const double dr = (double)rt - (double)r[u];
+            const double dy = (double)yt - (double)y[u];
+            sums[1] += dr * dr / (double)tbr[u] + ds2t;
+            sums[2] += dy * dy / (double)eb[u];
+            sums[3] += fabs(dr * ((double)sg[u] * dr));
+            sums[4] += fabs(dr * dy) + fabs(ds * dy);
+          }
+        }
+      }
     }
-    // A' y_tr (the row pass ended with a barrier: y_tr is complete)
+    __syncthreads();
+    // A' y_tr, then the x-block acceptance sums
     {
       const gp<const T> ytg = G(w.Y[nxt]);
       const lp<T> sy = ly;
@@ -912,19 +946,34 @@ struct BSolver {
         if constexpr (STAGE) return sy[col];
         else return ytg[col];
       };
-      const gp<const T> Xn = G(w.X[nxt]), Xc = G(w.X[cur]), QXn = G(w.QX[nxt]),
-                        QXc = G(w.QX[cur]), ATYc = G(w.ATY[cur]);
       const gp<T> ATYn = G(w.ATY[nxt]);
-      const double gid = gamma_inv;
       rows<T, false>(I.AT, at_vals(), prodT, [&](int col, T a) { return a * yat(col); },
-                     [&](int i, T a) {
-                       ATYn[i] = a;
-                       const double dx = (double)Xn[i] - (double)Xc[i];
-                       const double hdx = ((double)QXn[i] - (double)QXc[i]) + gid * dx;
-                       const double ady = (double)a - (double)ATYc[i];
-                       sums[5] += fabs(dx * hdx);
-                       sums[6] += fabs(dx * ady);
-                     });
+                     [&](int i, T a) { ATYn[i] = a; });
+      const gp<const T> Xn = G(w.X[nxt]), Xc = G(w.X[cur]), QXn = G(w.QX[nxt]),
+                        QXc = G(w.QX[cur]), ATYc = G(w.ATY[cur]), ATYr = G(w.ATY[nxt]);
+      const double gid = gamma_inv;
+      for (int i0 = threadIdx.x; i0 < n; i0 += U * BT) {
+        T xn[U], xc[U], qn[U], qc[U], an[U], ac[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * BT;
+          if (i < n) {
+            xn[u] = Xn[i]; xc[u] = Xc[i]; qn[u] = QXn[i]; qc[u] = QXc[i]; an[u] = ATYr[i];
+            ac[u] = ATYc[i];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * BT;
+          if (i < n) {
+            const double dx = (double)xn[u] - (double)xc[u];
+            const double hdx = ((double)qn[u] - (double)qc[u]) + gid * dx;
+            const double ady = (double)an[u] - (double)ac[u];
+            sums[5] += fabs(dx * hdx);
+            sums[6] += fabs(dx * ady);
+          }
+        }
+      }
     }
     allreduce<7>(sums, 0u);
     decide(sums);

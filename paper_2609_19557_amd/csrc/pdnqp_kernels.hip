@@ -274,6 +274,30 @@ __global__ __launch_bounds__(kBlock) void k_penalty(Ctrl *__restrict__ c, InnerP
   if (moved) atomicOr(&c->pen_moved, 1);
 }
 
+// min (as 1 / max 1/sigma), sum and max of the row penalties into gen[5],
+// gen[6], gen[7]
+__global__ __launch_bounds__(kBlock) void k_sigma_stats(Ctrl *c, const double *sig, int32_t m,
+                                                        double *partial) {
+  double a[3] = {0.0, 0.0, 0.0};  // max(1 / sigma), sum, max(sigma); sigma > 0
+  for_elems(m, blockIdx.x, gridDim.x, [&](int j) {
+    const double s = sig[j];
+    a[0] = fmax(a[0], 1.0 / s);
+    a[1] += s;
+    a[2] = fmax(a[2], s);
+  });
+  block_reduce<3>(a, 0x5u, partial, blockIdx.x);
+  if (last_block(&c->ticket[TK_GEN], gridDim.x)) {
+    double r[3];
+    final_reduce<3>(partial, gridDim.x, 0x5u, r);
+    if (threadIdx.x == 0) {
+      c->gen[5] = 1.0 / r[0];
+      c->gen[6] = r[1];
+      c->gen[7] = r[2];
+      c->ticket[TK_GEN] = 0;
+    }
+  }
+}
+
 // ===========================================================================
 // Anderson acceleration of the outer duals and the centre (Section 3.2,
 // "Anderson acceleration"): Type-II mixing over the stored points.
@@ -636,6 +660,11 @@ void launch_penalty(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v
   if (p.m == 0) return;
   hipLaunchKernelGGL(k_penalty, dim3(nz(pr.blocks)), dim3(kBlock), 0, st, c, p, v, have_prev,
                      rnorm, theta, growth, sig_max, gate, gate_tol);
+}
+
+void launch_sigma_stats(hipStream_t st, Ctrl *c, const double *sig, int32_t m, double *partial) {
+  const int blocks = (int)std::min<int64_t>(((int64_t)m + kBlock - 1) / kBlock, 1024);
+  hipLaunchKernelGGL(k_sigma_stats, dim3(nz(blocks)), dim3(kBlock), 0, st, c, sig, m, partial);
 }
 
 void launch_aa_pack(hipStream_t st, double *dst, const double *lam, const double *z, int32_t m,

@@ -229,6 +229,8 @@ void launch_penalty(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v
                     const Part &pr, int have_prev, double rnorm, double theta, double growth,
                     double sig_max, int gate, double gate_tol);
 void launch_copy(hipStream_t st, double *dst, const double *src, int32_t n);
+// min, sum and max of sigma (m > 0) into c->gen[5..7]
+void launch_sigma_stats(hipStream_t st, Ctrl *c, const double *sig, int32_t m, double *partial);
 // Anderson: dst = (lam, z); Gram of the residual differences of the points
 // slot[0..p] (oldest first) of the histories U, G (row stride len);
 // combination G_p - sum gamma_j (G_{j+1} - G_j) into (lam, z) with

@@ -613,7 +613,7 @@ int Solver::run_inner(double deadline, std::string &err, const IterVecs<T> &iv, 
   for (;;) {
     const int t = hctrl_->t, tc = hctrl_->t_call;
     int slots = st_.check_every - (t % st_.check_every);
-    slots = std::min(slots, st_.max_inner - tc);
+    slots = std::min(slots, ip_.max_inner - tc);
     slots = std::max(slots, 1);
     // with profiling on, one chunk in `profile` is launched directly so that
     // its slots can be sampled
@@ -750,9 +750,21 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   int status = PDNQP_MAX_ITER;
   int64_t k = 0;
   double rp = NAN, rd = NAN, sp = NAN, sd = NAN;
+  // learned controller state
+  const bool ctl_on = st_.controller == 1 && ctl_loaded_;
+  bool ctl_fallback = false;
+  int ctl_stall = 0;
+  double ctl_best = std::numeric_limits<double>::infinity();
+  double rp_prev = NAN;
+  log_n_ = 0;
+  log_feat_.assign((size_t)std::max(0, st_.outer_log) * PDNQP_FEATURES, 0.0);
+  log_rec_.assign((size_t)std::max(0, st_.outer_log) * PDNQP_OUTER_RECORD, 0.0);
+  ip_.max_inner = st_.max_inner;
   while (k < st_.max_outer) {
     ip_.delta_a = delta_a;
     ip_.delta_r = delta_r;
+    const double delta_used = delta_a;
+    const int64_t acc_before = hctrl_->accepted, rst_before = hctrl_->restarts;
     if (need_form) {
       if (st_.anderson_mem > 0) anderson_form();
       form_inner(gamma);
@@ -776,7 +788,9 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       status = PDNQP_TIME_LIMIT;
       break;
     }
-    if (ist == ST_ITER_LIMIT) {
+    // with the learned controller, the inner iteration budget ends the inner
+    // solve like its stopping test
+    if (ist == ST_ITER_LIMIT && !(ctl_on && !ctl_fallback)) {
       // keep the outer variables and continue the inner solve
       need_form = false;
       hctrl_->state = ST_RUNNING;
@@ -802,6 +816,35 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     sd = std::max({1.0, ov[5], c_norm_, ov[6]});
     const double dxz = ov[7];
     const double rn = m ? ov[3] : 0.0;
+    // controller features of this outer step (and the outer log)
+    float feat[PDNQP_FEATURES];
+    if (ctl_on || log_n_ < st_.outer_log) {
+      double smin = 1.0, smean = 1.0, smax = 1.0;
+      if (m) {
+        launch_sigma_stats(stream_, ctrl_, v_.sigma, m, v_.partial);
+        if ((r = read_ctrl(err))) return r;
+        smin = hctrl_->gen[5];
+        smean = hctrl_->gen[6] / m;
+        smax = hctrl_->gen[7];
+      }
+      auto lg = [](double v) { return std::log10(std::max(v, 1e-30)); };
+      const double inner_step = (double)(hctrl_->accepted - acc_before);
+      const double rst_step = (double)(hctrl_->restarts - rst_before);
+      double f[PDNQP_FEATURES] = {
+          lg(rp), lg(rd), lg(sp), lg(sd), lg(dxz / gamma), lg(delta_used), lg(eps_ak),
+          lg(hctrl_->omega), lg(smin), lg(smean), lg(smax),
+          std::isfinite(rp_prev) ? lg(rp) - lg(rp_prev) : 0.0,
+          std::isfinite(rd_prev) ? lg(rd) - lg(rd_prev) : 0.0,
+          std::log10(1.0 + inner_step), std::log10(1.0 + rst_step), std::log10(1.0 + (double)k)};
+      for (int i = 0; i < PDNQP_FEATURES; ++i) feat[i] = (float)f[i];
+      if (log_n_ < st_.outer_log) {
+        std::memcpy(&log_feat_[(size_t)log_n_ * PDNQP_FEATURES], f, sizeof(f));
+        const double rec[PDNQP_OUTER_RECORD] = {rp, rd, sp, sd, hctrl_->omega, inner_step,
+                                                rst_step, delta_used};
+        std::memcpy(&log_rec_[(size_t)log_n_ * PDNQP_OUTER_RECORD], rec, sizeof(rec));
+        log_n_ += 1;
+      }
+    }
     if (st_.verbose) {
       std::fprintf(stderr,
                    "[pdnqp] outer %lld  r_p %.3e (tol %.3e)  r_d %.3e (tol %.3e)  inner %lld  "
@@ -843,6 +886,38 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     if (st_.anderson_mem > 0 &&
         (r = anderson(rp, rd, sp, eps_abs, eps_rel, rd_prev, err)))
       return r;
+    // learned controller: next inner tolerance, iteration budget and primal
+    // weight; after 3 outer steps without progress of the outer KKT measure
+    // the adaptive rule takes over for the rest of the solve
+    if (ctl_on && !ctl_fallback) {
+      const double kkt = std::max(rp / (eps_abs + eps_rel * sp), rd / (eps_abs + eps_rel * sd));
+      if (kkt < ctl_best) {
+        ctl_best = kkt;
+        ctl_stall = 0;
+      } else if (++ctl_stall >= 3) {
+        ctl_fallback = true;
+        ip_.max_inner = st_.max_inner;
+      }
+    }
+    if (ctl_on && !ctl_fallback) {
+      float y[3];
+      hipMemcpyAsync(ctl_x_, feat, sizeof(feat), hipMemcpyHostToDevice, stream_);
+      mlp_forward_device(stream_, ctl_theta_, ctl_x_, ctl_y_);
+      hipMemcpyAsync(y, ctl_y_, sizeof(y), hipMemcpyDeviceToHost, stream_);
+      if ((r = check(hipStreamSynchronize(stream_), "controller", err))) return r;
+      auto clampd = [](double v, double lo, double hi) {
+        return std::isfinite(v) ? std::min(std::max(v, lo), hi) : hi;
+      };
+      const double dl = std::exp(clampd((double)y[0], -60.0, 0.0));
+      delta_a = std::max(eps_abs, dl);
+      delta_r = std::max(eps_rel, dl);
+      ip_.max_inner = (int32_t)clampd(std::exp(clampd((double)y[1], 0.0, 30.0)),
+                                      (double)st_.check_every, (double)st_.max_inner);
+      hctrl_->omega = std::exp(clampd((double)y[2], -9.2, 9.2));
+      hipMemcpyAsync(&ctrl_->omega, &hctrl_->omega, sizeof(double), hipMemcpyHostToDevice,
+                     stream_);
+    }
+    rp_prev = rp;
     rd_prev = rd;
     need_form = true;
     if (now_s() > deadline) {
@@ -875,6 +950,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   oc.trace_trials = hctrl_->trace_trials_n;
   oc.trace_checks = hctrl_->trace_checks_n;
   oc.anderson_steps = aa_steps_;
+  oc.controller_fallback = ctl_fallback ? 1 : 0;
   if ((r = finish(oc, x_out, lam_out, info, err))) return r;
   if (info) info->solve_s = now_s() - t_start;
   return PDNQP_OK;
@@ -936,6 +1012,8 @@ int Solver::finish(const Outcome &oc, double *x_out, double *lam_out, pdnqp_info
     info->omega = oc.omega;
     info->setup_s = oc.setup_s;
     info->anderson_steps = oc.anderson_steps;
+    info->controller_fallback = oc.controller_fallback;
+    info->outer_logged = log_n_;
     external_check(xs, lam_orig, info);
   }
   return PDNQP_OK;
@@ -1226,6 +1304,38 @@ int Solver::anderson(double rp, double rd, double sp, double eps_abs, double eps
   aa_rd_ = rd;
   aa_steps_ += 1;
   return check(hipGetLastError(), "anderson kernels", err);
+}
+
+// ===========================================================================
+// Learned controller parameters and the outer-step log.
+// ===========================================================================
+int Solver::set_controller(const float *theta, std::string &err) {
+  if (!ctl_theta_) {
+    ctl_theta_ = (float *)dalloc((size_t)PDNQP_MLP_PARAMS * 4);
+    ctl_x_ = (float *)dalloc(PDNQP_FEATURES * 4);
+    ctl_y_ = (float *)dalloc(16);
+    if (!ctl_theta_ || !ctl_x_ || !ctl_y_) {
+      err = "device allocation failed";
+      return PDNQP_E_NOMEM;
+    }
+  }
+  int r = check(hipMemcpyAsync(ctl_theta_, theta, (size_t)PDNQP_MLP_PARAMS * 4,
+                               hipMemcpyHostToDevice, stream_),
+                "controller upload", err);
+  if (r) return r;
+  r = check(hipStreamSynchronize(stream_), "controller upload", err);
+  if (r) return r;
+  ctl_loaded_ = true;
+  return PDNQP_OK;
+}
+
+int Solver::outer_log(int32_t *steps, double *feat, double *rec) const {
+  if (steps) *steps = log_n_;
+  if (feat && log_n_)
+    std::memcpy(feat, log_feat_.data(), (size_t)log_n_ * PDNQP_FEATURES * sizeof(double));
+  if (rec && log_n_)
+    std::memcpy(rec, log_rec_.data(), (size_t)log_n_ * PDNQP_OUTER_RECORD * sizeof(double));
+  return PDNQP_OK;
 }
 
 }  // namespace pdnqp

@@ -49,6 +49,7 @@ struct Outcome {
   double setup_s = 0;
   int32_t trace_iters = 0, trace_trials = 0, trace_checks = 0;
   int32_t anderson_steps = 0;
+  int32_t controller_fallback = 0;
 };
 
 class Solver {
@@ -172,9 +173,28 @@ class Solver {
   double aa_rp_ = 0.0, aa_rd_ = 0.0;
   int aa_steps_ = 0;
   void anderson_form();
+  // learned controller (settings.controller) and the outer-step log
+  float *ctl_theta_ = nullptr, *ctl_x_ = nullptr, *ctl_y_ = nullptr;
+  bool ctl_loaded_ = false;
+  std::vector<double> log_feat_, log_rec_;
+  int32_t log_n_ = 0;
+
+ public:
+  int set_controller(const float *theta, std::string &err);
+  int outer_log(int32_t *steps, double *feat, double *rec) const;
+
+ private:
   int anderson(double rp, double rd, double sp, double eps_abs, double eps_rel, double rd_prev,
                std::string &err);
 };
+
+// The controller network (pdnqp_mlp.hip).
+void mlp_forward_device(hipStream_t st, const float *theta, const float *x, float *y);
+int mlp_forward(const float *theta, const float *X, int count, float *Y, std::string &err);
+int mlp_gradient(const float *theta, const float *X, const float *Y, int count, float *grad,
+                 double *loss, std::string &err);
+int mlp_train(float *theta, const float *X, const float *Y, int count, int epochs, int batch,
+              float lr, uint64_t seed, float *loss_curve, std::string &err);
 
 // Batched persistent solve over several handles (pdnqp_batch_host.cpp).
 struct BatchRequest {

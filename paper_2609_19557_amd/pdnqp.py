@@ -67,6 +67,8 @@ class Settings(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("anderson_mem", ctypes.c_int32),
         ("anderson_reg", ctypes.c_double),
+        ("controller", ctypes.c_int32),
+        ("outer_log", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),
@@ -98,6 +100,8 @@ class Info(ctypes.Structure):
         ("omega", ctypes.c_double),
         ("setup_s", ctypes.c_double),
         ("solve_s", ctypes.c_double),
+        ("controller_fallback", ctypes.c_int32),
+        ("outer_logged", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -136,7 +140,11 @@ class BatchReport(ctypes.Structure):
 EXPORTED = ["pdnqp_default_settings", "pdnqp_settings_size", "pdnqp_info_size", "pdnqp_create",
             "pdnqp_solve", "pdnqp_solve_batch", "pdnqp_destroy", "pdnqp_last_error",
             "pdnqp_dims", "pdnqp_get_trace", "pdnqp_kernel_stats", "pdnqp_batch_last_report",
-            "pdnqp_batch_set_config", "pdnqp_batch_autotune"]
+            "pdnqp_batch_set_config", "pdnqp_batch_autotune", "pdnqp_mlp_forward",
+            "pdnqp_mlp_gradient", "pdnqp_mlp_train", "pdnqp_set_controller",
+            "pdnqp_get_outer_log"]
+
+MLP_PARAMS, N_FEATURES, OUTER_RECORD = 5443, 16, 8
 
 _lib = None
 
@@ -184,6 +192,16 @@ def load(path=None):
     lib.pdnqp_batch_set_config.restype = ctypes.c_int
     lib.pdnqp_batch_autotune.argtypes = [i32, P(vp), i32, P(i32), P(i32), vp]
     lib.pdnqp_batch_autotune.restype = ctypes.c_int
+    lib.pdnqp_mlp_forward.argtypes = [vp, vp, i32, vp]
+    lib.pdnqp_mlp_forward.restype = ctypes.c_int
+    lib.pdnqp_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, P(dbl)]
+    lib.pdnqp_mlp_gradient.restype = ctypes.c_int
+    lib.pdnqp_mlp_train.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
+    lib.pdnqp_mlp_train.restype = ctypes.c_int
+    lib.pdnqp_set_controller.argtypes = [vp, vp]
+    lib.pdnqp_set_controller.restype = ctypes.c_int
+    lib.pdnqp_get_outer_log.argtypes = [vp, P(i32), vp, vp]
+    lib.pdnqp_get_outer_log.restype = ctypes.c_int
     if lib.pdnqp_settings_size() != ctypes.sizeof(Settings):
         raise ImportError("pdnqp_settings layout mismatch between library and binding")
     if lib.pdnqp_info_size() != ctypes.sizeof(Info):
@@ -316,6 +334,27 @@ class Solver:
             raise _err(self.lib, code)
         return dict(w=w, y=y[:, :mint], trials=tr, checks=ck)
 
+    def set_controller(self, theta):
+        """Loads the controller network's parameters (MLP_PARAMS floats)."""
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        code = self.lib.pdnqp_set_controller(self.h, _ptr(th))
+        if code != OK:
+            raise _err(self.lib, code)
+
+    def outer_log(self):
+        """Features (steps x 16) and raw records (steps x 8) of the outer
+        steps recorded by the last solve (settings.outer_log)."""
+        n = ctypes.c_int32()
+        code = self.lib.pdnqp_get_outer_log(self.h, ctypes.byref(n), None, None)
+        if code != OK:
+            raise _err(self.lib, code)
+        f = np.zeros((max(n.value, 1), N_FEATURES))
+        r = np.zeros((max(n.value, 1), OUTER_RECORD))
+        self.lib.pdnqp_get_outer_log(self.h, ctypes.byref(n), _ptr(f), _ptr(r))
+        return f[:n.value], r[:n.value]
+
     def kernel_stats(self):
         cnt = ctypes.c_int32()
         self.lib.pdnqp_kernel_stats(self.h, None, 0, ctypes.byref(cnt))
@@ -397,3 +436,44 @@ def batch_autotune(solvers, probe_inner=64):
     if code != OK:
         raise _err(lib, code)
     return (blk.value, wv.value), ms.tolist()
+
+
+def mlp_forward(theta, X):
+    """Controller network on the GPU: (count x 16) -> (count x 3)."""
+    lib = load()
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.zeros((X.shape[0], 3), dtype=np.float32)
+    code = lib.pdnqp_mlp_forward(_ptr(th), _ptr(X), X.shape[0], _ptr(Y))
+    if code != OK:
+        raise _err(lib, code)
+    return Y
+
+
+def mlp_gradient(theta, X, Y):
+    """Gradient and value of the mean squared error, on the GPU."""
+    lib = load()
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    loss = ctypes.c_double()
+    code = lib.pdnqp_mlp_gradient(_ptr(th), _ptr(X), _ptr(Y), X.shape[0], _ptr(g),
+                                  ctypes.byref(loss))
+    if code != OK:
+        raise _err(lib, code)
+    return g, loss.value
+
+
+def mlp_train(theta, X, Y, epochs=200, batch=256, lr=1e-3, seed=0):
+    """Adam training on the GPU; returns (theta, loss per epoch)."""
+    lib = load()
+    th = np.array(theta, dtype=np.float32, copy=True)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.ascontiguousarray(Y, dtype=np.float32)
+    curve = np.zeros(max(epochs, 1), dtype=np.float32)
+    code = lib.pdnqp_mlp_train(_ptr(th), _ptr(X), _ptr(Y), X.shape[0], int(epochs), int(batch),
+                               float(lr), int(seed), _ptr(curve))
+    if code != OK:
+        raise _err(lib, code)
+    return th, curve[:epochs]
