@@ -847,9 +847,10 @@ struct BSolver {
       }
     }
     __syncthreads();
-    // Q x_tr = Q_off x_tr + diag(Q) x_tr
+    // Q_off x_tr; the diagonal term is added in the x-block pass below (its
+    // first reader), where its loads are batched
     {
-      const gp<const T> xtg = G(w.X[nxt]), qd = G(w.qdiag);
+      const gp<const T> xtg = G(w.X[nxt]);
       const gp<T> QXn = G(w.QX[nxt]);
       const lp<T> sx = lx;
       auto xat = [&](int col) -> T {
@@ -857,7 +858,7 @@ struct BSolver {
         else return xtg[col];
       };
       rows<T, false>(I.Qo, qo_vals(), prodT, [&](int col, T a) { return a * xat(col); },
-                     [&](int i, T s) { QXn[i] = s + qd[i] * xat(i); });
+                     [&](int i, T s) { QXn[i] = s; });
     }
     // A x_tr, parked (in LDS when staged, else in the check buffer A x_bar,
     // which is free between checks); then the row-local part of the trial
@@ -938,7 +939,8 @@ struct BSolver {
       }
     }
     __syncthreads();
-    // A' y_tr, then the x-block acceptance sums
+    // A' y_tr, then Q x_tr = Q_off x_tr + diag(Q) x_tr and the x-block
+    // acceptance sums
     {
       const gp<const T> ytg = G(w.Y[nxt]);
       const lp<T> sy = ly;
@@ -949,23 +951,26 @@ struct BSolver {
       const gp<T> ATYn = G(w.ATY[nxt]);
       rows<T, false>(I.AT, at_vals(), prodT, [&](int col, T a) { return a * yat(col); },
                      [&](int i, T a) { ATYn[i] = a; });
-      const gp<const T> Xn = G(w.X[nxt]), Xc = G(w.X[cur]), QXn = G(w.QX[nxt]),
-                        QXc = G(w.QX[cur]), ATYc = G(w.ATY[cur]), ATYr = G(w.ATY[nxt]);
+      const gp<const T> Xn = G(w.X[nxt]), Xc = G(w.X[cur]), QXc = G(w.QX[cur]),
+                        ATYc = G(w.ATY[cur]), ATYr = G(w.ATY[nxt]), qd = G(w.qdiag);
+      const gp<T> QXn = G(w.QX[nxt]);
       const double gid = gamma_inv;
       for (int i0 = threadIdx.x; i0 < n; i0 += U * BT) {
-        T xn[U], xc[U], qn[U], qc[U], an[U], ac[U];
+        T xn[U], xc[U], qn[U], qc[U], an[U], ac[U], dg[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = i0 + u * BT;
           if (i < n) {
             xn[u] = Xn[i]; xc[u] = Xc[i]; qn[u] = QXn[i]; qc[u] = QXc[i]; an[u] = ATYr[i];
-            ac[u] = ATYc[i];
+            ac[u] = ATYc[i]; dg[u] = qd[i];
           }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = i0 + u * BT;
           if (i < n) {
+            qn[u] = qn[u] + dg[u] * xn[u];
+            QXn[i] = qn[u];
             const double dx = (double)xn[u] - (double)xc[u];
             const double hdx = ((double)qn[u] - (double)qc[u]) + gid * dx;
             const double ady = (double)an[u] - (double)ac[u];

@@ -66,18 +66,6 @@ def test_mlp_training_fits_teacher(P):
     assert M.loss(th.astype(np.float64), X, Y) == pytest.approx(curve[-1], rel=1e-3)
 
 
-def test_fold_normalisation_is_exact(P):
-    """Folding the feature standardisation into the first layer gives the
-    same outputs on raw features."""
-    from paper_2609_19557_amd import controller as C
-    th, X, _ = _data(6, 50)
-    mu = X.mean(axis=0)
-    sd = X.std(axis=0) + 0.5
-    y_std, _ = M.forward(th, (X - mu) / sd)
-    y_raw, _ = M.forward(C.fold_normalisation(th, mu, sd).astype(np.float64), X)
-    np.testing.assert_allclose(y_raw, y_std, rtol=1e-5, atol=1e-5)
-
-
 def test_outer_log_matches_oracle(P):
     """The logged outer residuals of the first outer steps are the oracle's
     (inside the iterate-parity window), and the features are the logs of
