@@ -113,7 +113,8 @@ def batch_leg(P, qpgen, args):
     ok = status == P.SOLVED
     for s in solvers:
         s.close()
-    idx = np.linspace(0, len(probs) - 1, max(1, args.batch_seq_sample)).astype(int)
+    idx = np.linspace(0, len(probs) - 1, args.batch_seq_sample).astype(int) \
+        if args.batch_seq_sample > 0 else np.zeros(0, dtype=int)
     seq = []
     for i in idx:
         s = P.Solver.from_problem(probs[i], precision=P.FP64, **kw)
@@ -121,7 +122,7 @@ def batch_leg(P, qpgen, args):
         _, _, inf = s.solve(1e-4, 1e-4)
         seq.append((time.perf_counter() - t1, inf["status"] == P.SOLVED))
         s.close()
-    seq_t = np.array([t for t, _ in seq])
+    seq_t = np.array([t for t, _ in seq]) if seq else np.zeros(1)
     return {
         "workload": (f"{len(probs)} instances, n_i ~ U{{200..20000}} (sum n {sum(p['n'] for p in probs):,}), "
                      f"m_i = n_i // 2, k_R = 5, k_A = 4, seed {args.seed}"),
@@ -138,9 +139,10 @@ def batch_leg(P, qpgen, args):
         "solve_s_p99": round(float(np.percentile(solve_s, 99)), 3),
         "solved_solve_s_p50": round(float(np.percentile(solve_s[ok], 50)), 3) if ok.any() else None,
         "inner_iters_per_s_aggregate": round(float(inner.sum()) / max(1e-9, wall), 1),
-        "sequential_fp64_sample": {"instances": len(seq), "mean_s": round(float(seq_t.mean()), 3),
-                                   "solved": int(sum(ok_ for _, ok_ in seq)),
-                                   "estimate_all_s": round(float(seq_t.mean()) * len(probs), 1)},
+        "sequential_fp64_sample": ({"instances": len(seq), "mean_s": round(float(seq_t.mean()), 3),
+                                    "solved": int(sum(ok_ for _, ok_ in seq)),
+                                    "estimate_all_s": round(float(seq_t.mean()) * len(probs), 1)}
+                                   if seq else None),
     }
 
 
@@ -164,7 +166,8 @@ def main():
     ap.add_argument("--batch-limit", type=float, default=30.0,
                     help="time limit per instance of the batched workload (s)")
     ap.add_argument("--batch-seq-sample", type=int, default=8,
-                    help="instances of the batch solved one after another in FP64 as baseline")
+                    help="instances of the batch solved one after another in FP64 as baseline "
+                         "(0: none)")
     ap.add_argument("--no-other-precision", action="store_true",
                     help="skip timing the other precision on the same instance")
     args = ap.parse_args()
