@@ -144,3 +144,42 @@ def test_null_handle_calls_are_errors(P):
     assert lib.pdnqp_solve(None, 1e-4, 1e-4, None, None, None, None, None) == -1
     assert lib.pdnqp_get_trace(None, None, None, None, None, None, None, None) == -1
     lib.pdnqp_destroy(None)
+
+
+@pytest.mark.parametrize("field,value", [("graph", 2), ("anderson_mem", 9), ("anderson_mem", -1),
+                                         ("anderson_reg", -1.0), ("controller", 2),
+                                         ("outer_log", -1), ("precision", 3)])
+def test_rejects_bad_extension_settings(P, field, value):
+    p = qpgen.workload("small", 3)
+    _expect_invalid(P, *_args(p), match="settings", **{field: value})
+
+
+def test_extension_defaults(P):
+    s = P.default_settings()
+    assert (s.graph, s.anderson_mem, s.controller, s.outer_log, s.precision) == (0, 0, 0, 0, 0)
+    assert s.anderson_reg == 1e-10
+
+
+def test_batch_and_network_argument_errors(P):
+    """Argument checks of the batched, tuning and network entry points that
+    fail before any device call."""
+    lib = P.load()
+    assert lib.pdnqp_batch_set_config(300, 1) == -1
+    assert lib.pdnqp_batch_set_config(512, 2) == -1
+    assert lib.pdnqp_batch_set_config(0, 0) == 0
+    assert lib.pdnqp_solve_batch(-1, None, 1e-4, 1e-4, None, None, None) == -1
+    assert lib.pdnqp_solve_batch(0, None, 1e-4, 1e-4, None, None, None) == 0
+    assert lib.pdnqp_solve_batch(0, None, 0.0, 0.0, None, None, None) == -1
+    assert lib.pdnqp_batch_autotune(0, None, 64, None, None, None) == -1
+    rep = P.pdnqp.BatchReport()
+    assert lib.pdnqp_batch_last_report(ctypes.byref(rep), None, 0) == 0
+    assert lib.pdnqp_mlp_forward(None, None, 1, None) == -1
+    th = np.zeros(P.MLP_PARAMS, dtype=np.float32)
+    x = np.zeros(16, dtype=np.float32)
+    y = np.zeros(3, dtype=np.float32)
+    assert lib.pdnqp_mlp_forward(th.ctypes.data, x.ctypes.data, 0, y.ctypes.data) == -1
+    assert lib.pdnqp_mlp_gradient(th.ctypes.data, x.ctypes.data, None, 1, None, None) == -1
+    assert lib.pdnqp_mlp_train(th.ctypes.data, x.ctypes.data, y.ctypes.data, 1, 1, 0,
+                               ctypes.c_float(1e-3), 0, None) == -1
+    assert lib.pdnqp_set_controller(None, th.ctypes.data) == -1
+    assert lib.pdnqp_get_outer_log(None, None, None, None) == -1
