@@ -107,7 +107,8 @@ typedef struct pdnqp_settings {
                               (pdnqp_kernel_stats); 0: off */
   int32_t trace_iters;     /* record unscaled inner (w, y) after each of the first N accepted trials */
   int32_t trace_trials;    /* record (L, R, accepted) of the first N trials and the first N checks */
-  int32_t verbose;         /* 1: one line per outer iteration on stderr */
+  int32_t verbose;         /* 1: one line per outer iteration on stderr; 2: also one line per
+                              inner call that ends at the max_inner limit */
   int32_t center_floor;    /* [reading] centre-update tolerances never fall below eps_abs, eps_rel; 1 */
   int32_t precision;       /* PDNQP_FP64 (default) or PDNQP_FP32: FP32 matrix values and inner
                               vectors, FP64 reductions, FP64 outer update and final check */
@@ -126,6 +127,10 @@ typedef struct pdnqp_settings {
                               progress of the outer KKT measure */
   int32_t outer_log;       /* record the controller features of the first N outer steps
                               (pdnqp_get_outer_log); 0 (default): none */
+  double fp32_promote;     /* with PDNQP_FP32: once the inner tolerances (max of the absolute
+                              and relative one) fall below this value, the rest of the solve
+                              runs the FP64 inner iteration (FP32 storage bounds the inner
+                              residual it can reach); 1e-5 (default); 0: never */
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */
@@ -159,6 +164,9 @@ typedef struct pdnqp_info {
   double solve_s;          /* seconds of the whole pdnqp_solve call */
   int32_t controller_fallback;  /* 1 if the learned controller handed over to the adaptive rule */
   int32_t outer_logged;    /* outer steps recorded for pdnqp_get_outer_log */
+  int32_t promoted_outer;  /* with PDNQP_FP32: the outer step from which the inner iteration ran
+                              in FP64 (settings.fp32_promote); 0: none */
+  int32_t reserved2;
 } pdnqp_info;
 
 /* Writes the defaults into *s.  Never fails. */

@@ -233,43 +233,68 @@ struct BSolver {
   // (or max when MAX) of entry(col, val) over the row's entries, passed to
   // fin(row, acc) on one thread.  S is the staging type.  Ends with a
   // barrier, so fin's writes are visible to the whole workgroup afterwards.
+  //
+  // Row block b holds rows [rb[b], rb[b+1]) (at most 2 BT of them) and
+  // nonzeros [tb[b], tb[b+1]).  While block b is staged and summed, the
+  // indices, values and row bounds of block b+1 and the extent of block b+2
+  // are in flight: no load that a block's own sums depend on is issued in
+  // that block's iteration.
   template <typename S, bool MAX, typename V, typename P, typename Fn>
   __device__ __forceinline__ void rows(const BCsr &M, const V *val_, lp<S> stage, P &&entry,
                                        Fn &&fin) {
     const gp<const int32_t> rp = G(M.p);
     const gp<const int32_t> ci = G(M.i);
     const gp<const int32_t> rb = G(M.rb);
+    const gp<const int32_t> tb = G(M.tb);
     const gp<const V> val = G(val_);
     const int nrb = uni(M.nrb);
     if (nrb <= 0) return;
-    // the next tile's indices and values are loaded before the current tile
-    // is staged and summed, so their latency overlaps that work
     int col[E], ncol[E];
     V vv[E], nvv[E];
-    int r0 = uni(rb[0]), r1 = uni(rb[1]);
-    int base = uni(rp[r0]);
-    int cnt = uni(rp[r1]) - base;
-    auto load_tile = [&](int bs, int cn, int (&cc)[E], V (&vl)[E]) {
+    // row bounds of this thread's rows t and t + BT of a block: p[row], p[row + 1]
+    int bnd[4], nbnd[4];
+    auto load_block = [&](int r0_, int r1_, int bs, int cn, int (&cc)[E], V (&vl)[E],
+                          int (&bd)[4]) {
+      if (cn <= TILE) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int k = e * BT + threadIdx.x;
-        cc[e] = 0;
-        vl[e] = V(0);
-        if (k < cn) {
-          cc[e] = __builtin_nontemporal_load(&ci[bs + k]);
-          vl[e] = __builtin_nontemporal_load(&val[bs + k]);
+        for (int e = 0; e < E; ++e) {
+          const int k = e * BT + threadIdx.x;
+          cc[e] = 0;
+          vl[e] = V(0);
+          if (k < cn) {
+            cc[e] = __builtin_nontemporal_load(&ci[bs + k]);
+            vl[e] = __builtin_nontemporal_load(&val[bs + k]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int row = r0_ + j * BT + (int)threadIdx.x;
+        bd[2 * j] = 0;
+        bd[2 * j + 1] = 0;
+        if (row < r1_) {
+          bd[2 * j] = rp[row];
+          bd[2 * j + 1] = rp[row + 1];
         }
       }
     };
-    if (cnt <= TILE) load_tile(base, cnt, col, vv);
+    int r0 = uni(rb[0]), r1 = uni(rb[1]);
+    int base = uni(tb[0]), end = uni(tb[1]);
+    int r2 = 0, end2 = 0;  // end of the block after this one
+    if (nrb > 1) {
+      r2 = uni(rb[2]);
+      end2 = uni(tb[2]);
+    }
+    load_block(r0, r1, base, end - base, col, vv, bnd);
     for (int bk = 0; bk < nrb; ++bk) {
-      int nr0 = 0, nr1 = 0, nbase = 0, ncnt = 0;
+      const int cnt = end - base;
+      const int nr0 = r1, nr1 = r2, nbase = end, nend = end2;
       if (bk + 1 < nrb) {
-        nr0 = r1;
-        nr1 = uni(rb[bk + 2]);
-        nbase = uni(rp[nr0]);
-        ncnt = uni(rp[nr1]) - nbase;
-        if (ncnt <= TILE) load_tile(nbase, ncnt, ncol, nvv);
+        load_block(nr0, nr1, nbase, nend - nbase, ncol, nvv, nbnd);
+        if (bk + 2 < nrb) {
+          r2 = uni(rb[bk + 3]);
+          end2 = uni(tb[bk + 3]);
+        }
       }
       if (cnt <= TILE) {
 #pragma unroll
@@ -278,14 +303,17 @@ struct BSolver {
           if (k < cnt) stage[k] = entry(col[e], vv[e]);
         }
         __syncthreads();
-#pragma unroll 1
-        for (int row = r0 + (int)threadIdx.x; row < r1; row += BT) {
-          const int a = rp[row] - base;
-          const int b = rp[row + 1] - base;
-          S acc = S(0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int row = r0 + j * BT + (int)threadIdx.x;
+          if (row < r1) {
+            const int a = bnd[2 * j] - base;
+            const int b = bnd[2 * j + 1] - base;
+            S acc = S(0);
 #pragma unroll 4
-          for (int k = a; k < b; ++k) acc = MAX ? vmax<S>(acc, stage[k]) : acc + stage[k];
-          fin(row, acc);
+            for (int k = a; k < b; ++k) acc = MAX ? vmax<S>(acc, stage[k]) : acc + stage[k];
+            fin(row, acc);
+          }
         }
         __syncthreads();
       } else {
@@ -303,12 +331,14 @@ struct BSolver {
       r0 = nr0;
       r1 = nr1;
       base = nbase;
-      cnt = ncnt;
+      end = nend;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         col[e] = ncol[e];
         vv[e] = nvv[e];
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bnd[j] = nbnd[j];
     }
   }
 

@@ -17,7 +17,8 @@ namespace pdnqp {
 struct BCsr {
   const int32_t *p;
   const int32_t *i;
-  const int32_t *rb;  // block b owns rows [rb[b], rb[b+1])
+  const int32_t *rb;  // block b owns rows [rb[b], rb[b+1]) (at most 2 rows per thread)
+  const int32_t *tb;  // and nonzeros [tb[b], tb[b+1]): tb[b] = p[rb[b]]
   int32_t rows;
   int32_t nrb;
 };

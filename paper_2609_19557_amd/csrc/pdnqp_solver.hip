@@ -493,7 +493,7 @@ void Solver::form_inner(double gamma) {
   launch_steps(stream_, ip_, v_, Q_, A_, AT_, 1.0 / gamma, st_.step_boost);
   InnerParams pi = ip_;
   pi.mode_init = 1;
-  if (fp32_) {
+  if (bulk32_) {
     // per-outer-step data and the warm-started state into the FP32 bulk buffers
     const int32_t n = qp_.n, m = qp_.m, mi = qp_.mi;
     launch_cast<float, double>(stream_, iv32_.sigma, v_.sigma, m);
@@ -760,7 +760,17 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   log_feat_.assign((size_t)std::max(0, st_.outer_log) * PDNQP_FEATURES, 0.0);
   log_rec_.assign((size_t)std::max(0, st_.outer_log) * PDNQP_OUTER_RECORD, 0.0);
   ip_.max_inner = st_.max_inner;
+  bulk32_ = fp32_;
+  int32_t promoted_outer = 0;
   while (k < st_.max_outer) {
+    // FP32 storage bounds the inner residual the FP32 iteration can reach:
+    // below the promotion level the inner iteration continues in FP64 (the
+    // FP64 copy of the iterate is current after every FP32 inner call)
+    if (bulk32_ && std::max(delta_a, delta_r) < st_.fp32_promote) {
+      bulk32_ = false;
+      promoted_outer = (int32_t)(k + 1);
+      need_form = true;
+    }
     ip_.delta_a = delta_a;
     ip_.delta_r = delta_r;
     const double delta_used = delta_a;
@@ -772,7 +782,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       if ((r = read_ctrl(err))) return r;
     }
     int ist;
-    if (fp32_) {
+    if (bulk32_) {
       ist = run_inner<float>(deadline, err, iv32_, Qo32_, A32_, AT32_);
       if (ist > -1000) cast_state_to64(hctrl_->cur);
     } else {
@@ -792,6 +802,14 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     // solve like its stopping test
     if (ist == ST_ITER_LIMIT && !(ctl_on && !ctl_fallback)) {
       // keep the outer variables and continue the inner solve
+      if (st_.verbose >= 2) {
+        std::fprintf(stderr,
+                     "[pdnqp] inner call %lld hit the iteration limit: inner %lld  restarts %lld  "
+                     "omega %.3g  %.2fs\n",
+                     (long long)k, (long long)hctrl_->accepted, (long long)hctrl_->restarts,
+                     hctrl_->omega, now_s() - t_start);
+        std::fflush(stderr);
+      }
       need_form = false;
       hctrl_->state = ST_RUNNING;
       hctrl_->t_call = 0;
@@ -951,6 +969,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   oc.trace_checks = hctrl_->trace_checks_n;
   oc.anderson_steps = aa_steps_;
   oc.controller_fallback = ctl_fallback ? 1 : 0;
+  oc.promoted_outer = promoted_outer;
   if ((r = finish(oc, x_out, lam_out, info, err))) return r;
   if (info) info->solve_s = now_s() - t_start;
   return PDNQP_OK;
@@ -1014,6 +1033,7 @@ int Solver::finish(const Outcome &oc, double *x_out, double *lam_out, pdnqp_info
     info->anderson_steps = oc.anderson_steps;
     info->controller_fallback = oc.controller_fallback;
     info->outer_logged = log_n_;
+    info->promoted_outer = oc.promoted_outer;
     external_check(xs, lam_orig, info);
   }
   return PDNQP_OK;
@@ -1101,21 +1121,23 @@ int Solver::batch_prepare(double eps_abs, double eps_rel, const double *x0, cons
   if (m && e == hipSuccess)
     e = hipMemcpyAsync(v_.lam, lam0i.data(), m * 8, hipMemcpyHostToDevice, stream_);
   if ((r = check(e, "upload x0/lambda0", err))) return r;
-  // row blocks of the launch's tile
+  // row blocks of the launch's tile (at most two rows per thread), each
+  // followed by the blocks' first nonzeros
   const int tile = batch_tile(block);
   BatchBlocks *bb = nullptr;
   for (auto &x : bblocks_)
-    if (x.tile == tile) bb = &x;
+    if (x.block == block) bb = &x;
   if (!bb) {
     BatchBlocks nb;
-    nb.tile = tile;
+    nb.block = block;
     auto build = [&](const std::vector<int32_t> &rp, int32_t rows, int32_t *&dev,
                      int32_t &nrb) -> bool {
-      std::vector<int32_t> rb(rows + 2);
-      stream_row_blocks(rp.data(), rows, 4 * block, &nrb, rb.data(), tile);
-      dev = (int32_t *)dalloc((size_t)(nrb + 1) * 4);
+      std::vector<int32_t> rb(2 * (size_t)rows + 4);
+      stream_row_blocks(rp.data(), rows, 2 * block, &nrb, rb.data(), tile);
+      for (int32_t b = 0; b <= nrb; ++b) rb[nrb + 1 + b] = rp[rb[b]];
+      dev = (int32_t *)dalloc((size_t)(nrb + 1) * 8);
       if (!dev) return false;
-      return hipMemcpyAsync(dev, rb.data(), (size_t)(nrb + 1) * 4, hipMemcpyHostToDevice,
+      return hipMemcpyAsync(dev, rb.data(), (size_t)(nrb + 1) * 8, hipMemcpyHostToDevice,
                             stream_) == hipSuccess;
     };
     if (!build(qp_.Qp, n, nb.q, nb.nq) || !build(qp_.Qop, n, nb.qo, nb.nqo) ||
@@ -1144,10 +1166,10 @@ int Solver::batch_prepare(double eps_abs, double eps_rel, const double *x0, cons
   // an infinite limit becomes 3600 s: every workgroup of the launch ends
   const double lim = std::isfinite(st_.time_limit_s) ? std::min(st_.time_limit_s, 1e9) : 3600.0;
   bi.limit_ticks = (uint64_t)(lim * ticks_per_s);
-  bi.Q = BCsr{Qp_, Qi_, bb->q, n, bb->nq};
-  bi.Qo = BCsr{Qop_, Qoi_, bb->qo, n, bb->nqo};
-  bi.A = BCsr{Ap_, Ai_, bb->a, m, bb->na};
-  bi.AT = BCsr{ATp_, ATi_, bb->at, n, bb->nat};
+  bi.Q = BCsr{Qp_, Qi_, bb->q, bb->q + bb->nq + 1, n, bb->nq};
+  bi.Qo = BCsr{Qop_, Qoi_, bb->qo, bb->qo + bb->nqo + 1, n, bb->nqo};
+  bi.A = BCsr{Ap_, Ai_, bb->a, bb->a + bb->na + 1, m, bb->na};
+  bi.AT = BCsr{ATp_, ATi_, bb->at, bb->at + bb->nat + 1, n, bb->nat};
   bi.atperm = atperm_;
   bi.Qraw = Qraw_;
   bi.Qoraw = Qoraw_;

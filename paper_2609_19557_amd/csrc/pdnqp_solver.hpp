@@ -50,6 +50,7 @@ struct Outcome {
   int32_t trace_iters = 0, trace_trials = 0, trace_checks = 0;
   int32_t anderson_steps = 0;
   int32_t controller_fallback = 0;
+  int32_t promoted_outer = 0;
 };
 
 class Solver {
@@ -128,6 +129,7 @@ class Solver {
   Csr Q_{}, A_{}, AT_{}, Qr_{}, Ar_{}, ATr_{}, Qo_{};
   // FP32 bulk path
   bool fp32_ = false;
+  bool bulk32_ = false;  // this outer step's inner iteration runs in FP32 (fp32_ until promoted)
   IterVecs<float> iv32_{};
   CsrT<float> Qo32_{}, A32_{}, AT32_{};
   float *Qo32v_ = nullptr, *A32v_ = nullptr, *AT32v_ = nullptr;
@@ -157,7 +159,7 @@ class Solver {
                     const CsrT<T> &AT);
   // batched path: row blocks per tile size (Q, Q_off, A, A'), Lanczos coefficients
   struct BatchBlocks {
-    int tile = 0;
+    int block = 0;
     int32_t *q = nullptr, *qo = nullptr, *a = nullptr, *at = nullptr;
     int32_t nq = 0, nqo = 0, na = 0, nat = 0;
   };

@@ -69,6 +69,7 @@ class Settings(ctypes.Structure):
         ("anderson_reg", ctypes.c_double),
         ("controller", ctypes.c_int32),
         ("outer_log", ctypes.c_int32),
+        ("fp32_promote", ctypes.c_double),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),
@@ -102,6 +103,8 @@ class Info(ctypes.Structure):
         ("solve_s", ctypes.c_double),
         ("controller_fallback", ctypes.c_int32),
         ("outer_logged", ctypes.c_int32),
+        ("promoted_outer", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -91,3 +91,35 @@ def test_fp32_medium_first_iterations(P):
     for k in range(20):
         assert _relmax(t["w"][k], tr.w[k]) <= 1e-4, f"w at {k}"
         assert _relmax(t["y"][k], tr.y[k]) <= 1e-4, f"y at {k}"
+
+
+def test_fp32_promotes_below_its_attainable_tolerance(P):
+    """At 1e-4 the FP32 run never promotes.  At 1e-6 the inner tolerance
+    falls below the promotion level (1e-5), the inner iteration continues in
+    FP64 from the FP32 iterate, and the solve meets the tight test.  Up to
+    the promotion the run is the plain FP32 one."""
+    prob = qpgen.workload("small", 1)
+    kw = dict(precision=P.FP32, outer_scaling=P.SCALE_RUIZ_QA, time_limit_s=60.0)
+    s = P.Solver.from_problem(prob, **kw)
+    _, _, info = s.solve(1e-4, 1e-4)
+    assert info["status"] == O.SOLVED and info["promoted_outer"] == 0
+    s = P.Solver.from_problem(prob, **kw)
+    x, lam, info = s.solve(1e-6, 1e-6)
+    assert info["status"] == O.SOLVED
+    assert info["promoted_outer"] >= 1
+    assert info["r_p_scaled"] <= 1e-6 + 1e-6 * info["s_p_scaled"]
+    assert info["r_d_scaled"] <= 1e-6 + 1e-6 * info["s_d_scaled"]
+    rp, rd, _, _ = O.external_kkt(prob, x, lam)
+    assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
+    # the FP64 inner iteration before promotion is the plain FP32 one: a run
+    # stopped one outer step before the promotion takes the same path
+    k = info["promoted_outer"]
+    if k > 1:
+        a = P.Solver.from_problem(prob, max_outer=k - 1, **kw)
+        xa, _, ia = a.solve(1e-6, 1e-6)
+        b = P.Solver.from_problem(prob, max_outer=k - 1, fp32_promote=0.0, **kw)
+        xb, _, ib = b.solve(1e-6, 1e-6)
+        assert ia["promoted_outer"] == 0 and ib["promoted_outer"] == 0
+        assert np.array_equal(xa, xb)
+    print(f"promoted at outer step {k} of {info['outer_iters']}; "
+          f"unscaled r_p {rp:.2e} r_d {rd:.2e}")
