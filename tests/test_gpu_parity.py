@@ -195,6 +195,16 @@ def _edge_cases():
     Ar.data = rng.normal(size=Ar.nnz)
     cases["ragged_tail_rows"] = _custom(nr, Ar, Ar @ np.full(nr, 0.5) - 0.2,
                                         np.full(517, np.inf), 9)
+    # a row longer than any stream tile (4500 nonzeros), next to short rows
+    nd = 4500
+    Ad = sp.vstack([sp.csr_matrix(rng.normal(size=(1, nd))),
+                    sp.random(3, nd, density=3.0 / nd, random_state=10, format="csr")]).tocsr()
+    xd = rng.uniform(0.2, 0.8, nd)
+    axd = Ad @ xd
+    cases["row_longer_than_tile"] = _custom(
+        nd, Ad, np.concatenate([axd[:1], axd[1:] - 0.1]),
+        np.concatenate([axd[:1], np.full(3, np.inf)]), 12,
+        Qd=sp.diags(rng.uniform(0.5, 2.0, nd)).tocsr())
     return cases
 
 
