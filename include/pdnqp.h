@@ -128,9 +128,11 @@ typedef struct pdnqp_settings {
   int32_t outer_log;       /* record the controller features of the first N outer steps
                               (pdnqp_get_outer_log); 0 (default): none */
   double fp32_promote;     /* with PDNQP_FP32: once the inner tolerances (max of the absolute
-                              and relative one) fall below this value, the rest of the solve
+                              and relative one) fall to this value or below, the rest of the solve
                               runs the FP64 inner iteration (FP32 storage bounds the inner
                               residual it can reach); 1e-5 (default); 0: never */
+  double delta_floor;      /* [reading] the inner tolerances never fall below delta_floor times
+                              eps_abs, eps_rel (inner-tolerance-factor states no floor); 1 */
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */

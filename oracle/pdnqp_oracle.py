@@ -96,6 +96,9 @@ class Settings:
     # [reading] the centre-update tolerances are floored at the outer
     # tolerances eps_abs, eps_rel (like the inner tolerances)
     center_floor: bool = True
+    # [reading] the inner tolerances never fall below delta_floor times the
+    # outer tolerances eps_abs, eps_rel
+    delta_floor: float = 1.0
     # [reading] Lanczos steps for the smallest eigenvalue of Q
     lanczos_iters: int = 100
     gamma_override: float = 0.0
@@ -818,12 +821,12 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
         r_prev = r_row
         penalties_moved = bool(np.any(sigma != sigma_before))
         # eq. (inner-tolerance-factor); [reading] ratio 1 when r_d = 0,
-        # tolerances floored at the outer tolerances
+        # tolerances floored at delta_floor times the outer tolerances
         dxz = _ninf(x_new - z)
         ratio = 1.0 if rd == 0 else min(1.0, dxz / gamma / rd)
         rho = st.rho_in_max - (st.rho_in_max - st.rho_in_min) * ratio
-        delta_a = max(st.eps_abs, rho * delta_a)
-        delta_r = max(st.eps_rel, rho * delta_r)
+        delta_a = max(st.delta_floor * st.eps_abs, rho * delta_a)
+        delta_r = max(st.delta_floor * st.eps_rel, rho * delta_r)
         # eq. (center-update) / (center-tolerance-update)
         if rp <= eps_ak + eps_rk * sp_:
             z = x_new.copy()

@@ -1714,8 +1714,8 @@ struct BSolver {
       // inner tolerances (inner-tolerance-factor)
       const double ratio = (rd == 0.0) ? 1.0 : fmin(1.0, dxz / gamma / rd);
       const double rho = I.st.rho_in_max - (I.st.rho_in_max - I.st.rho_in_min) * ratio;
-      delta_a = fmax(eps_abs, rho * delta_a);
-      delta_r = fmax(eps_rel, rho * delta_r);
+      delta_a = fmax(I.st.delta_floor * eps_abs, rho * delta_a);
+      delta_r = fmax(I.st.delta_floor * eps_rel, rho * delta_r);
       // proximal centre (center-update)
       if (rp <= eps_ak + eps_rk * sp) {
         const gp<double> z = G(I.v.z);

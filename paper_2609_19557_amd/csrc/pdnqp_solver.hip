@@ -764,9 +764,9 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   int32_t promoted_outer = 0;
   while (k < st_.max_outer) {
     // FP32 storage bounds the inner residual the FP32 iteration can reach:
-    // below the promotion level the inner iteration continues in FP64 (the
+    // at or below the promotion level the inner iteration continues in FP64 (the
     // FP64 copy of the iterate is current after every FP32 inner call)
-    if (bulk32_ && std::max(delta_a, delta_r) < st_.fp32_promote) {
+    if (bulk32_ && std::max(delta_a, delta_r) <= st_.fp32_promote) {
       bulk32_ = false;
       promoted_outer = (int32_t)(k + 1);
       need_form = true;
@@ -888,8 +888,8 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     // inner tolerances (inner-tolerance-factor)
     const double ratio = (rd == 0.0) ? 1.0 : std::min(1.0, dxz / gamma / rd);
     const double rho = st_.rho_in_max - (st_.rho_in_max - st_.rho_in_min) * ratio;
-    delta_a = std::max(eps_abs, rho * delta_a);
-    delta_r = std::max(eps_rel, rho * delta_r);
+    delta_a = std::max(st_.delta_floor * eps_abs, rho * delta_a);
+    delta_r = std::max(st_.delta_floor * eps_rel, rho * delta_r);
     // proximal centre (center-update)
     if (rp <= eps_ak + eps_rk * sp) {
       launch_copy(stream_, v_.z, v_.X[hctrl_->cur], n);
@@ -927,8 +927,8 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
         return std::isfinite(v) ? std::min(std::max(v, lo), hi) : hi;
       };
       const double dl = std::exp(clampd((double)y[0], -60.0, 0.0));
-      delta_a = std::max(eps_abs, dl);
-      delta_r = std::max(eps_rel, dl);
+      delta_a = std::max(st_.delta_floor * eps_abs, dl);
+      delta_r = std::max(st_.delta_floor * eps_rel, dl);
       ip_.max_inner = (int32_t)clampd(std::exp(clampd((double)y[1], 0.0, 30.0)),
                                       (double)st_.check_every, (double)st_.max_inner);
       hctrl_->omega = std::exp(clampd((double)y[2], -9.2, 9.2));

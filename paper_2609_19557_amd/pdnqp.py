@@ -70,6 +70,7 @@ class Settings(ctypes.Structure):
         ("controller", ctypes.c_int32),
         ("outer_log", ctypes.c_int32),
         ("fp32_promote", ctypes.c_double),
+        ("delta_floor", ctypes.c_double),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),

@@ -150,7 +150,8 @@ def test_null_handle_calls_are_errors(P):
                                          ("anderson_reg", -1.0), ("controller", 2),
                                          ("outer_log", -1), ("precision", 3),
                                          ("fp32_promote", -1e-5),
-                                         ("fp32_promote", float("nan"))])
+                                         ("fp32_promote", float("nan")),
+                                         ("delta_floor", 0.0), ("delta_floor", float("inf"))])
 def test_rejects_bad_extension_settings(P, field, value):
     p = qpgen.workload("small", 3)
     _expect_invalid(P, *_args(p), match="settings", **{field: value})
@@ -161,6 +162,7 @@ def test_extension_defaults(P):
     assert (s.graph, s.anderson_mem, s.controller, s.outer_log, s.precision) == (0, 0, 0, 0, 0)
     assert s.anderson_reg == 1e-10
     assert s.fp32_promote == 1e-5
+    assert s.delta_floor == 1.0
 
 
 def test_batch_and_network_argument_errors(P):

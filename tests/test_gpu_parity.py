@@ -40,7 +40,7 @@ def _gpu_kwargs(st: O.Settings):
             "rho_in_max", "rho_z", "check_every", "max_rejects", "restart_suff", "restart_nec",
             "restart_art", "shrink_safety", "shrink_min", "shrink_max", "omega0", "sigma_growth",
             "sigma_max", "sigma0_min", "sigma0_max", "lanczos_iters", "gamma_override",
-            "step_boost", "outer_scaling", "anderson_mem", "anderson_reg"]
+            "step_boost", "outer_scaling", "anderson_mem", "anderson_reg", "delta_floor"]
     kw = {k: getattr(st, k) for k in keys}
     kw["max_outer"] = int(min(st.max_outer, 2**62))
     kw["penalty_gate"] = int(st.penalty_gate)
