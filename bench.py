@@ -206,6 +206,8 @@ def main():
 
     kernels = []
     for k in ks:
+        if k["launches"] == 0:  # the separate decision launch when it is fused
+            continue
         gbs = k["bytes_per_launch"] / (k["avg_us"] * 1e-6) / 1e9 if k["avg_us"] > 0 else 0.0
         kernels.append({"name": k["name"], "launches": k["launches"],
                         "avg_us": round(k["avg_us"], 3), "total_ms": round(k["total_ms"], 3),
@@ -269,7 +271,8 @@ def main():
                  "steps": io["outer_iters"], "inner_accepted": io["inner_accepted"],
                  "kernels": [{"name": k["name"], "avg_us": round(k["avg_us"], 3),
                               "GBps": round(k["bytes_per_launch"] / (k["avg_us"] * 1e-6) / 1e9, 1)
-                              if k["avg_us"] > 0 else 0.0} for k in so.kernel_stats()]}
+                              if k["avg_us"] > 0 else 0.0} for k in so.kernel_stats()
+                             if k["launches"] > 0]}
         so.close()
         print(f"[bench] other precision: {other}", file=sys.stderr, flush=True)
 
