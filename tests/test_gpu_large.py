@@ -1,0 +1,79 @@
+"""Parity at the benchmark's full size: the large workload (n = 1,000,000,
+m = 500,000, nnz(Q) = 5M, nnz(A) = 4M, seed 1) in the launch configuration
+the benchmark times (default settings), against the FP64 oracle over the
+first 12 accepted inner iterations of the first outer step (inner limit 12,
+so the check at the inner limit runs too).
+
+FP64: every recorded iterate (w and y, all 2.25M entries each) matches at
+1e-9 relative, with identical accept/reject and check decisions.  FP32 bulk:
+the same iterates at 1e-4.  Both: the library's final KKT report equals the
+oracle's formula evaluated on the returned point.
+"""
+
+import numpy as np
+import pytest
+
+import qpgen
+from oracle import pdnqp_oracle as O
+from tests.test_gpu_parity import (_gpu_kwargs, assert_decision_parity, assert_iterate_parity,
+                                   window_of)
+
+pytestmark = pytest.mark.gpu
+
+ITERS = 12
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_19557_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def large_case():
+    prob = qpgen.workload("large", 1)
+    st = O.Settings(max_outer=1, max_inner=ITERS)
+    tr = O.Trace(max_iters=ITERS)
+    res = O.solve(prob, st, trace=tr)
+    return prob, st, tr, res
+
+
+def _run(P, prob, st, precision):
+    s = P.Solver.from_problem(prob, trace_iters=ITERS, trace_trials=4 * ITERS,
+                              precision=precision, profile=32, **_gpu_kwargs(st))
+    x, lam, info = s.solve(st.eps_abs, st.eps_rel)
+    return s, x, lam, info
+
+
+def _check_report(prob, x, lam, info):
+    rp, rd, sp_, sd = O.external_kkt(prob, x, lam)
+    assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
+    assert info["r_d"] == pytest.approx(rd, rel=1e-6, abs=1e-12)
+    assert np.all(x >= prob["xl"]) and np.all(x <= prob["xu"])
+
+
+def test_large_fp64_first_iterations(P, large_case):
+    prob, st, tr, res = large_case
+    assert len(tr.w) == ITERS
+    s, x, lam, info = _run(P, prob, st, P.FP64)
+    t = s.trace()
+    assert_iterate_parity(tr, t, n_expect=ITERS)
+    assert_decision_parity(tr, t, window_of(tr))
+    assert info["status"] == res.status
+    np.testing.assert_allclose(x, res.x, atol=1e-9 * max(1.0, np.abs(res.x).max()))
+    _check_report(prob, x, lam, info)
+
+
+def test_large_fp32_first_iterations(P, large_case):
+    prob, st, tr, res = large_case
+    s, x, lam, info = _run(P, prob, st, P.FP32)
+    t = s.trace()
+    assert t["w"].shape[0] == ITERS
+    for k in range(ITERS):
+        W, Y = np.asarray(tr.w[k]), np.asarray(tr.y[k])
+        dw = np.abs(t["w"][k] - W).max() / max(1.0, np.abs(W).max())
+        dy = np.abs(t["y"][k] - Y).max() / max(1.0, np.abs(Y).max())
+        assert dw <= 1e-4 and dy <= 1e-4, (k, dw, dy)
+    assert info["status"] == res.status
+    _check_report(prob, x, lam, info)
