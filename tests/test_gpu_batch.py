@@ -97,6 +97,22 @@ def test_batch_fp64_unstaged_matches_oracle(P, parity_case):
     assert_decision_parity(tr, t, window_of(tr))
 
 
+def test_batch_large_next_to_small(P):
+    """One launch with a large unstaged instance (n = 70000) next to small
+    staged ones: each follows the oracle."""
+    probs = [qpgen.random_indefinite_qp(70000, 35000, 5, 4, 4, instance=0),
+             qpgen.random_indefinite_qp(500, 250, 5, 4, 4, instance=1),
+             qpgen.random_indefinite_qp(900, 450, 5, 4, 4, instance=2)]
+    st = O.Settings(max_outer=2, max_inner=64, outer_scaling=2)
+    solvers, out, rep = _solve_batch(P, probs, st, (512, 1), trace_iters=40, trace_trials=120)
+    for p, s in zip(probs, solvers):
+        tr = O.Trace(max_iters=40)
+        O.solve(p, st, trace=tr)
+        t = s.trace()
+        assert_iterate_parity(tr, t, n_expect=40)
+        assert_decision_parity(tr, t, window_of(tr))
+
+
 def test_batch_fp64_full_solves(P):
     probs = _batch(11, 4, 200, 700)
     st = O.Settings(outer_scaling=2, max_outer=5000, time_limit=120.0)
