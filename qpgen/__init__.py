@@ -145,6 +145,71 @@ def batch(seed, count=512, lo=200, hi=20000):
             for i, ni in enumerate(sizes)]
 
 
+FAMILY_FLOW = 2
+
+
+def flow_qp(seed, n_target=1_000_000):
+    """Concave-cost multistage flow, after the paper's appendix on the
+    million-variable models (flow family) and its scenario-distribution
+    table: minimise sum_e (c_e f_e - alpha c_e / u_e f_e^2) subject to
+    B f = b (node-arc incidence, one equality row per node) and
+    0 <= f <= u.
+
+    Network: L layers of width w; each of three carriers joins layer l to
+    layer l+1 through its own seeded permutation of the w nodes, so there
+    are n = 3 w (L-1) arcs and m = L w nodes.  Scenario draws (in this
+    order): L in {4, 6, 8, 12, 16}, alpha ~ U(0.03, 0.24), base cost
+    ~ U(0.05, 0.30), capacity ratio rho ~ U(1.05, 1.80), stage growth
+    g ~ U(0, 0.12), carrier-cost ratio ~ U(1/(1-2 alpha) + 0.25,
+    1/(1-2 alpha) + 2), reference-flow interval bounds ~ U(0.30, 1.00) and
+    U(1.20, 3.00), then one reference flow h_k per carrier uniform in that
+    interval.
+
+    Readings where the description leaves the construction open: carrier k
+    costs base * ratio^k * (1 + g)^l on stage l; every arc of carrier k
+    carries the reference flow h_k and has capacity rho * h_k; b = B f0, so
+    the reference flow f0 is feasible (it is returned as ``x0``, the
+    model's frozen start).
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), FAMILY_FLOW]))
+    L = int(rng.choice([4, 6, 8, 12, 16]))
+    alpha = rng.uniform(0.03, 0.24)
+    base = rng.uniform(0.05, 0.30)
+    rho = rng.uniform(1.05, 1.80)
+    growth = rng.uniform(0.0, 0.12)
+    r0 = 1.0 / (1.0 - 2.0 * alpha)
+    ratio = rng.uniform(r0 + 0.25, r0 + 2.0)
+    h_lo = rng.uniform(0.30, 1.00)
+    h_hi = rng.uniform(1.20, 3.00)
+    h = rng.uniform(h_lo, h_hi, size=3)
+    w = max(1, n_target // (3 * (L - 1)))
+    n = 3 * w * (L - 1)
+    m = L * w
+    tails = np.empty(n, dtype=np.int64)
+    heads = np.empty(n, dtype=np.int64)
+    f0 = np.empty(n)
+    cost = np.empty(n)
+    e = 0
+    for stage in range(L - 1):
+        for k in range(3):
+            perm = rng.permutation(w)
+            tails[e:e + w] = stage * w + np.arange(w)
+            heads[e:e + w] = (stage + 1) * w + perm
+            f0[e:e + w] = h[k]
+            cost[e:e + w] = base * ratio ** k * (1.0 + growth) ** stage
+            e += w
+    u = rho * f0
+    arcs = np.arange(n)
+    B = sp.csr_matrix((np.concatenate([-np.ones(n), np.ones(n)]),
+                       (np.concatenate([tails, heads]), np.concatenate([arcs, arcs]))),
+                      shape=(m, n))
+    B = _canonical(B)
+    b = B @ f0
+    Q = _canonical(sp.diags(-2.0 * alpha * cost / u, format="csr"))
+    return dict(n=n, m=m, Q=Q, A=B, c=cost, xl=np.zeros(n), xu=u, rl=b.copy(), ru=b.copy(),
+                x0=f0, seed=seed, layers=L, width=w, alpha=alpha)
+
+
 def tiny_qp(n, m_e, m_i, seed, density=0.6, neg_shift=1.0, box=(0.0, 1.0)):
     """Small dense-ish instance for brute-force checks (n <= 8).
 
