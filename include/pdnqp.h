@@ -95,7 +95,7 @@ typedef struct pdnqp_settings {
   double shrink_max;       /*   0.9 */
   double omega0;           /* [reading] initial primal weight, 1 */
   double sigma_growth;     /* [reading] penalty growth multiplier, 10 */
-  double sigma_max;        /* [reading] penalty cap, 1e9 */
+  double sigma_max;        /* [reading] penalty cap, 1e4 (the upper clamp of the initial penalty) */
   double sigma0_min;       /* [reading] clamp of the initial penalty, 1e-4 */
   double sigma0_max;       /*   1e4 */
   int32_t penalty_gate;    /* [reading] rows already within the outer tolerance are not penalised further, 1 */
@@ -133,6 +133,12 @@ typedef struct pdnqp_settings {
                               residual it can reach); 1e-5 (default); 0: never */
   double delta_floor;      /* [reading] the inner tolerances never fall below delta_floor times
                               eps_abs, eps_rel (inner-tolerance-factor states no floor); 1 */
+  int32_t fp32_stall;      /* with PDNQP_FP32: after this many outer steps without a 10% gain of
+                              the outer KKT measure max(r_p/(eps_abs+eps_rel s_p),
+                              r_d/(eps_abs+eps_rel s_d)), the rest of the solve runs the FP64 inner
+                              iteration (FP32 rounding of the iterate can stall the outer
+                              iteration above the tolerance); 50 (default); 0: never */
+  int32_t reserved_s;
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */

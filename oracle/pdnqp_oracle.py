@@ -87,7 +87,7 @@ class Settings:
     omega0: float = 1.0
     # [reading] penalty growth and clamps
     sigma_growth: float = 10.0
-    sigma_max: float = 1e9
+    sigma_max: float = 1e4
     sigma0_min: float = 1e-4
     sigma0_max: float = 1e4
     # [reading] a row whose residual already meets the outer tolerance

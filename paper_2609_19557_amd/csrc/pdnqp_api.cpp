@@ -116,7 +116,7 @@ void pdnqp_default_settings(pdnqp_settings *s) {
   s->shrink_max = 0.9;
   s->omega0 = 1.0;
   s->sigma_growth = 10.0;
-  s->sigma_max = 1e9;
+  s->sigma_max = 1e4;
   s->sigma0_min = 1e-4;
   s->sigma0_max = 1e4;
   s->penalty_gate = 1;
@@ -129,6 +129,7 @@ void pdnqp_default_settings(pdnqp_settings *s) {
   s->anderson_reg = 1e-10;
   s->fp32_promote = 1e-5;
   s->delta_floor = 1.0;
+  s->fp32_stall = 50;
 }
 
 size_t pdnqp_settings_size(void) { return sizeof(pdnqp_settings); }
@@ -157,7 +158,7 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         (st.graph != 0 && st.graph != 1) || st.anderson_mem < 0 ||
         st.anderson_mem > PDNQP_ANDERSON_MAX || !(st.anderson_reg >= 0) ||
         (st.controller != 0 && st.controller != 1) || st.outer_log < 0 ||
-        !(st.fp32_promote >= 0) || !(st.delta_floor > 0) || !std::isfinite(st.delta_floor))
+        !(st.fp32_promote >= 0) || !(st.delta_floor > 0) || !std::isfinite(st.delta_floor) || st.fp32_stall < 0)
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);

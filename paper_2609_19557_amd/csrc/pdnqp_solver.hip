@@ -762,6 +762,8 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   ip_.max_inner = st_.max_inner;
   bulk32_ = fp32_;
   int32_t promoted_outer = 0;
+  double p32_best = std::numeric_limits<double>::infinity();
+  int p32_stall = 0;
   while (k < st_.max_outer) {
     // FP32 storage bounds the inner residual the FP32 iteration can reach:
     // at or below the promotion level the inner iteration continues in FP64 (the
@@ -875,6 +877,18 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     if (rp <= eps_abs + eps_rel * sp && rd <= eps_abs + eps_rel * sd) {
       status = PDNQP_SOLVED;
       break;
+    }
+    // FP32 bulk that no longer improves the outer KKT measure hands the rest
+    // of the solve to the FP64 inner iteration (from the next formation)
+    if (bulk32_ && st_.fp32_stall > 0) {
+      const double kkt = std::max(rp / (eps_abs + eps_rel * sp), rd / (eps_abs + eps_rel * sd));
+      if (kkt < 0.9 * p32_best) {
+        p32_best = kkt;
+        p32_stall = 0;
+      } else if (++p32_stall >= st_.fp32_stall) {
+        bulk32_ = false;
+        promoted_outer = (int32_t)(k + 1);
+      }
     }
     // row penalties (penalty-trigger-eq)
     if (st_.anderson_mem > 0) {

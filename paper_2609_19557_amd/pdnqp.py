@@ -71,6 +71,8 @@ class Settings(ctypes.Structure):
         ("outer_log", ctypes.c_int32),
         ("fp32_promote", ctypes.c_double),
         ("delta_floor", ctypes.c_double),
+        ("fp32_stall", ctypes.c_int32),
+        ("reserved_s", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),

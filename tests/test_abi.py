@@ -151,7 +151,8 @@ def test_null_handle_calls_are_errors(P):
                                          ("outer_log", -1), ("precision", 3),
                                          ("fp32_promote", -1e-5),
                                          ("fp32_promote", float("nan")),
-                                         ("delta_floor", 0.0), ("delta_floor", float("inf"))])
+                                         ("delta_floor", 0.0), ("delta_floor", float("inf")),
+                                         ("fp32_stall", -1)])
 def test_rejects_bad_extension_settings(P, field, value):
     p = qpgen.workload("small", 3)
     _expect_invalid(P, *_args(p), match="settings", **{field: value})
@@ -163,6 +164,7 @@ def test_extension_defaults(P):
     assert s.anderson_reg == 1e-10
     assert s.fp32_promote == 1e-5
     assert s.delta_floor == 1.0
+    assert s.fp32_stall == 50
 
 
 def test_batch_and_network_argument_errors(P):

@@ -1,4 +1,6 @@
-"""Parity at the benchmark's full size: the large workload (n = 1,000,000,
+"""Full-size runs (n about 1M).
+
+Parity at the benchmark's full size: the large workload (n = 1,000,000,
 m = 500,000, nnz(Q) = 5M, nnz(A) = 4M, seed 1) in the launch configuration
 the benchmark times (default settings), against the FP64 oracle over the
 first 12 accepted inner iterations of the first outer step (inner limit 12,
@@ -8,6 +10,9 @@ FP64: every recorded iterate (w and y, all 2.25M entries each) matches at
 1e-9 relative, with identical accept/reject and check decisions.  FP32 bulk:
 the same iterates at 1e-4.  Both: the library's final KKT report equals the
 oracle's formula evaluated on the returned point.
+
+Time to tolerance at full size on the flow-family stand-in (999,990 arcs):
+full solves to 1e-4 in FP64, and in FP32 bulk through its hand-over to FP64.
 """
 
 import numpy as np
@@ -77,3 +82,37 @@ def test_large_fp32_first_iterations(P, large_case):
         assert dw <= 1e-4 and dy <= 1e-4, (k, dw, dy)
     assert info["status"] == res.status
     _check_report(prob, x, lam, info)
+
+
+@pytest.fixture(scope="module")
+def flow_case():
+    return qpgen.flow_qp(101)
+
+
+def test_flow_family_million_solves(P, flow_case):
+    """The flow-family stand-in at n = 999,990 arcs (m = 355,552 node rows)
+    from its feasible reference flow: FP64 reaches the 1e-4 test, and the
+    library's KKT report is the oracle's formula on the returned point."""
+    prob = flow_case
+    s = P.Solver.from_problem(prob, time_limit_s=120.0)
+    x, lam, info = s.solve(1e-4, 1e-4, x0=prob["x0"])
+    assert info["status"] == O.SOLVED
+    assert info["r_p_scaled"] <= 1e-4 + 1e-4 * info["s_p_scaled"]
+    assert info["r_d_scaled"] <= 1e-4 + 1e-4 * info["s_d_scaled"]
+    _check_report(prob, x, lam, info)
+    print(f"flow n={prob['n']}: {info['solve_s']:.2f} s, {info['outer_iters']} outer, "
+          f"{info['inner_accepted']} inner")
+
+
+def test_flow_family_fp32_promotes_on_stall(P, flow_case):
+    """FP32 bulk stalls above the tolerance on this instance (its rounding
+    keeps the dual residual near 3e-3); after 50 outer steps without a 10%
+    gain it hands over to the FP64 inner iteration and the solve succeeds."""
+    prob = flow_case
+    s = P.Solver.from_problem(prob, precision=P.FP32, time_limit_s=120.0)
+    x, lam, info = s.solve(1e-4, 1e-4, x0=prob["x0"])
+    assert info["status"] == O.SOLVED
+    assert info["promoted_outer"] > 0
+    _check_report(prob, x, lam, info)
+    print(f"flow n={prob['n']} FP32: promoted at outer step {info['promoted_outer']}, "
+          f"{info['solve_s']:.2f} s, {info['outer_iters']} outer")
