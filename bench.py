@@ -170,6 +170,8 @@ def main():
                          "(0: none)")
     ap.add_argument("--no-other-precision", action="store_true",
                     help="skip timing the other precision on the same instance")
+    ap.add_argument("--no-flow", action="store_true",
+                    help="skip the time to 1e-4 on the n ~ 1M flow-family stand-in")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -256,6 +258,29 @@ def main():
         st.close()
         print(f"[bench] time-to-1e-4: {ttt}", file=sys.stderr, flush=True)
 
+    # time to 1e-4 at n ~ 1M on the flow-family stand-in (concave-cost
+    # multistage flow), from its feasible reference flow, in both precisions
+    flow = None
+    if not args.no_flow:
+        fp = qpgen.flow_qp(101)
+        flow = {"workload": f"flow-family stand-in (concave-cost multistage flow, seed 101): "
+                            f"n={fp['n']:,} arcs, m={fp['m']:,} node rows, {fp['layers']} layers",
+                "tol": 1e-4, "start": "feasible reference flow", "outer_scaling": "ruiz_a (paper)"}
+        for pname, pr in (("fp64", P.FP64), ("fp32", P.FP32)):
+            sf = P.Solver.from_problem(fp, use_torch=True, time_limit_s=60.0, precision=pr)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            _, _, inf3 = sf.solve(1e-4, 1e-4, x0=fp["x0"])
+            torch.cuda.synchronize()
+            flow[pname] = {"seconds": round(time.perf_counter() - t3, 3),
+                           "status": inf3["status_name"], "outer_iters": inf3["outer_iters"],
+                           "inner_accepted": inf3["inner_accepted"], "r_p": inf3["r_p"],
+                           "r_d": inf3["r_d"], "s_p": inf3["s_p"], "s_d": inf3["s_d"],
+                           "promoted_outer": inf3["promoted_outer"]}
+            sf.close()
+        del fp
+        print(f"[bench] flow time-to-1e-4: {flow}", file=sys.stderr, flush=True)
+
     other = None
     if not args.no_other_precision:
         oprec = P.FP64 if args.precision == "fp32" else P.FP32
@@ -310,6 +335,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
+        "time_to_tol_flow": flow,
         "other_precision": other,
         "batch": batch,
         "trial": {"us_per_trial_kernels": round(trial_us, 3),
