@@ -3,7 +3,7 @@ FP64 outer update and final check) against the FP64 oracle.
 
 FP32 rounding (about 6e-8 per operation) is amplified along the trajectory
 like any perturbation, so iterates are compared at 1e-4 relative over the
-first accepted iterations, and full solves are judged by the termination
+first accepted iterations, and full solves are checked by the termination
 test and the FP64 KKT residuals of the returned point.  The stationary point
 an FP32 run reaches may differ from the FP64 one (the problem is nonconvex);
 the tests record the objective difference.
