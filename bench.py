@@ -174,7 +174,7 @@ def main():
                     help="skip the time to 1e-4 on the n ~ 1M flow-family stand-in")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding across GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
