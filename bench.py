@@ -155,7 +155,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--tol-time-limit", type=float, default=90.0)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32",
                     help="fp32: FP32 matrix values and inner vectors with FP64 reductions, FP64 "
