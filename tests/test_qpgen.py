@@ -44,6 +44,14 @@ def test_flow_structure(seed):
 
 
 def test_flow_small_instance_solves_on_the_oracle():
+    """The oracle solves a small flow instance from its reference flow to a
+    point whose unscaled dual residual is small in absolute terms too: with
+    the penalty cap reading (1e4) the multipliers stay bounded.  (With a 1e9
+    cap the penalties reached 8e8, the multipliers 5e4, and the relative test
+    accepted an absolute dual residual of 2.2.)"""
     p = qpgen.flow_qp(101, n_target=3000)
     res = O.solve(p, O.Settings(time_limit=120.0), x0=p["x0"])
     assert res.status == O.SOLVED
+    rp, rd, sp_, sd = O.external_kkt(p, res.x, res.lam)
+    assert rd <= 1e-3 and sd <= 10.0
+    assert np.abs(res.lam).max() <= 100.0
