@@ -33,7 +33,11 @@ Parity status of each reading: the restart rule, N_p = N_d, the rejection
 shrink factor, the initial primal weight, the objective scalar, the initial
 penalty, and the penalty growth factor are "parity unpinned" (the paper
 fixes no value to check against); the tests pin the mathematics around them
-(fixed point = KKT, brute-force minimisers, closed forms, invariants).
+(fixed point = KKT, brute-force minimisers, closed forms, invariants).  The
+outer rules the paper does state -- primal weight, inner-tolerance factor,
+penalty trigger, centre update, diagonal scales and steps -- are separate
+functions below, pinned by hand-computed values and by invariants along
+real runs.
 """
 
 from __future__ import annotations
@@ -494,6 +498,16 @@ def restart_metric_parts(si: ScaledInner, w, y):
     return float(pr @ pr), float(dr @ dr)
 
 
+def primal_weight_update(omega, d_w, d_y):
+    """eq. (primal-weight-update): when both movements of
+    eq. (primal-weight-movement) are nonzero, log(omega) moves a quarter of
+    the way towards log(d_y / d_w), the weight that balances the primal and
+    dual movements; otherwise omega is kept."""
+    if d_w > 0 and d_y > 0:
+        return math.exp(0.25 * math.log(d_y / d_w) + 0.75 * math.log(omega))
+    return omega
+
+
 def kkt_omega(parts, omega):
     p, d = parts
     return math.sqrt(omega * omega * p + d / (omega * omega))
@@ -513,6 +527,12 @@ class Trace:
     trials: list = field(default_factory=list)
     checks: list = field(default_factory=list)
     outer: list = field(default_factory=list)
+    # (omega before, omega after, d_w, d_y) at every restart
+    weights: list = field(default_factory=list)
+    # per completed outer step (first ``max_rules``): the inputs and results
+    # of the penalty, inner-tolerance and centre rules
+    max_rules: int = 0
+    rules: list = field(default_factory=list)
 
 
 @dataclass
@@ -634,11 +654,13 @@ def inner_solve(state: InnerState, omega, delta_a, delta_r, st: Settings,
                 parts = parts_a
             else:
                 parts = parts_c
+            # eq. (primal-weight-movement): movements since the last restart
             dW = float(np.linalg.norm(state.w - state.w_anchor))
             dY = float(np.linalg.norm(state.y - state.y_anchor))
-            if dW > 0 and dY > 0:
-                # eq. (primal-weight-update)
-                omega = math.exp(0.25 * math.log(dY / dW) + 0.75 * math.log(omega))
+            omega_before = omega
+            omega = primal_weight_update(omega, dW, dY)
+            if trace is not None:
+                trace.weights.append((omega_before, omega, dW, dY))
             state.tau, state.eta = diagonal_steps(si.m_w, si.m_y, omega, st)
             state.wbar, state.ybar = state.w.copy(), state.y.copy()
             state.N = 0
@@ -712,6 +734,53 @@ def outer_residuals(S: Scaled, x, lam):
     sp_ = max(1.0, _ninf(ax[:me]), _ninf(S.b[:me]), _ninf(ax[me:]), _ninf(S.b[me:]))
     sd = max(1.0, _ninf(qx), _ninf(S.c), _ninf(atl))
     return rp, rd, sp_, sd
+
+
+def penalty_update(sigma, r_new, r_prev, active, gate_tol, st: Settings):
+    """Row-wise penalty update (Section 3.2, eq. (penalty-trigger-eq)).
+
+    A row is raised when |r_i^{k+1}| > theta_sigma |r_i^k| (theta_sigma =
+    0.25), for every equality row and for an inequality row that is active;
+    every other penalty is unchanged.  ``active`` flags the rows that may be
+    raised (equality rows, and inequality rows with lambda_I < 0 [reading]).
+    [reading] growth sigma_i <- min(sigma_max, sigma_i max(1, growth
+    |r_i| / ||r||_inf)) (QPALM's rule with a smaller factor, as the paper
+    grows penalties more slowly than QPALM); with ``st.penalty_gate`` a row
+    whose residual already meets the outer tolerance (|r_i| <= gate_tol) is
+    not raised.  Returns (new sigma, triggered rows)."""
+    trig = (np.abs(r_new) > st.theta_sigma * np.abs(r_prev)) & active
+    if st.penalty_gate:
+        trig &= np.abs(r_new) > gate_tol
+    rn = _ninf(r_new)
+    if rn <= 0:
+        return sigma.copy(), np.zeros_like(trig)
+    fac = np.maximum(1.0, st.sigma_growth * np.abs(r_new) / rn)
+    return np.where(trig, np.minimum(st.sigma_max, sigma * fac), sigma), trig
+
+
+def inner_tolerance_factor(x_new, z, gamma, r_d, st: Settings):
+    """eq. (inner-tolerance-factor): rho = rho_max - (rho_max - rho_min)
+    min{1, gamma^{-1} ||x^{k+1} - z^k||_inf / r_d^{k+1}}.  [reading] the
+    ratio is 1 when r_d = 0."""
+    dxz = _ninf(x_new - z)
+    ratio = 1.0 if r_d == 0 else min(1.0, dxz / gamma / r_d)
+    return st.rho_in_max - (st.rho_in_max - st.rho_in_min) * ratio
+
+
+def center_update(x_new, z, r_p, s_p, eps_ak, eps_rk, st: Settings):
+    """eq. (center-update) and (center-tolerance-update): the centre moves to
+    x^{k+1} exactly when r_p <= eps_{a,k} + eps_{r,k} s_p, and after such a
+    move both centre tolerances are multiplied by rho_z.  [reading] with
+    ``st.center_floor`` they are floored at the outer tolerances.  Returns
+    (z, eps_a, eps_r, moved)."""
+    if r_p <= eps_ak + eps_rk * s_p:
+        eps_ak *= st.rho_z
+        eps_rk *= st.rho_z
+        if st.center_floor:
+            eps_ak = max(eps_ak, st.eps_abs)
+            eps_rk = max(eps_rk, st.eps_rel)
+        return x_new.copy(), eps_ak, eps_rk, True
+    return z, eps_ak, eps_rk, False
 
 
 @dataclass
@@ -806,35 +875,33 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
             x = x_new
             status = SOLVED
             break
-        # row-wise penalty update, eq. (penalty-trigger-eq)
+        # row-wise penalty update, eq. (penalty-trigger-eq); [reading] the
+        # first update is skipped (no previous residual yet)
         r_row = np.concatenate([ax[:me] - S.b[:me], ax[me:] - s_new])
         sigma_before = sigma
+        active = np.concatenate([np.ones(me, bool), lam[me:] < 0.0])
         if r_prev is not None:
-            rn = _ninf(r_row)
-            active = np.concatenate([np.ones(me, bool), lam[me:] < 0.0])
-            trig = (np.abs(r_row) > st.theta_sigma * np.abs(r_prev)) & active
-            if st.penalty_gate:
-                trig &= np.abs(r_row) > st.eps_abs + st.eps_rel * sp_
-            if rn > 0:
-                fac = np.maximum(1.0, st.sigma_growth * np.abs(r_row) / rn)
-                sigma = np.where(trig, np.minimum(st.sigma_max, sigma * fac), sigma)
-        r_prev = r_row
+            sigma, _ = penalty_update(sigma, r_row, r_prev, active,
+                                      st.eps_abs + st.eps_rel * sp_, st)
         penalties_moved = bool(np.any(sigma != sigma_before))
-        # eq. (inner-tolerance-factor); [reading] ratio 1 when r_d = 0,
-        # tolerances floored at delta_floor times the outer tolerances
-        dxz = _ninf(x_new - z)
-        ratio = 1.0 if rd == 0 else min(1.0, dxz / gamma / rd)
-        rho = st.rho_in_max - (st.rho_in_max - st.rho_in_min) * ratio
+        # eq. (inner-tolerance-factor); [reading] the inner tolerances are
+        # floored at delta_floor times the outer tolerances
+        rho = inner_tolerance_factor(x_new, z, gamma, rd, st)
         delta_a = max(st.delta_floor * st.eps_abs, rho * delta_a)
         delta_r = max(st.delta_floor * st.eps_rel, rho * delta_r)
         # eq. (center-update) / (center-tolerance-update)
-        if rp <= eps_ak + eps_rk * sp_:
-            z = x_new.copy()
-            eps_ak *= st.rho_z
-            eps_rk *= st.rho_z
-            if st.center_floor:
-                eps_ak = max(eps_ak, st.eps_abs)
-                eps_rk = max(eps_rk, st.eps_rel)
+        eps_before = (eps_ak, eps_rk)
+        z_old = z
+        z, eps_ak, eps_rk, moved = center_update(x_new, z, rp, sp_, eps_ak, eps_rk, st)
+        if trace is not None and len(trace.rules) < trace.max_rules:
+            trace.rules.append(dict(
+                k=k, rp=rp, rd=rd, sp=sp_, sd=sd, x=x_new.copy(), z_old=z_old.copy(),
+                z_new=z.copy(), gamma=gamma, rho=rho, delta=(delta_a, delta_r),
+                eps_before=eps_before, eps_after=(eps_ak, eps_rk), moved=moved,
+                r_row=r_row.copy(), r_prev=None if r_prev is None else r_prev.copy(),
+                active=active.copy(), sigma_before=sigma_before.copy(),
+                sigma_after=sigma.copy()))
+        r_prev = r_row
         # Anderson step on (lambda_E, lambda_I, z), Section 3.2
         if st.anderson_mem > 0:
             lam, z, aa_last = _anderson_outer(st, S, me, u_form, lam, z, rp, rd, sp_,

@@ -240,3 +240,37 @@ def tiny_qp(n, m_e, m_i, seed, density=0.6, neg_shift=1.0, box=(0.0, 1.0)):
                 A=_canonical(sp.csr_matrix(Ad)) if m else _canonical(sp.csr_matrix((0, n))),
                 c=c, xl=np.full(n, lo), xu=np.full(n, hi), rl=rl, ru=ru,
                 x_gen=x_in, seed=seed, instance=None)
+
+
+def tiny_general_qp(n, seed, kinds=("eq", "upper", "two")):
+    """Small instance (n <= 5) with one row of each requested kind:
+    ``"eq"`` (rl == ru), ``"lower"`` (only rl finite), ``"upper"`` (only ru
+    finite) or ``"two"`` (both finite, rl < ru).  Q, c and the box are drawn
+    as in :func:`tiny_qp`; every row holds at an interior point of the box.
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 98]))
+    G = rng.standard_normal((n, n))
+    Qd = 0.5 * (G + G.T) - np.eye(n)
+    m = len(kinds)
+    Ad = rng.standard_normal((m, n))
+    x_in = rng.uniform(0.2, 0.8, size=n)
+    ax = Ad @ x_in
+    rl = np.full(m, -np.inf)
+    ru = np.full(m, np.inf)
+    for j, kind in enumerate(kinds):
+        lo_gap, hi_gap = rng.uniform(0.0, 0.5, size=2)
+        if kind == "eq":
+            rl[j] = ru[j] = ax[j]
+        elif kind == "lower":
+            rl[j] = ax[j] - lo_gap
+        elif kind == "upper":
+            ru[j] = ax[j] + hi_gap
+        elif kind == "two":
+            rl[j] = ax[j] - lo_gap
+            ru[j] = ax[j] + hi_gap
+        else:
+            raise ValueError(kind)
+    c = rng.standard_normal(n)
+    return dict(n=n, m=m, Q=_canonical(sp.csr_matrix(Qd)), A=_canonical(sp.csr_matrix(Ad)),
+                c=c, xl=np.zeros(n), xu=np.ones(n), rl=rl, ru=ru, x_gen=x_in, seed=seed,
+                instance=None)

@@ -8,6 +8,9 @@ with the oracle or the library).
 * ``kkt_points``: every KKT point of a tiny QP (problem (qp) with
   stationarity (kkt-stationarity), lambda_I <= 0 and complementarity) by
   enumerating bound activity of x and activity of the inequality rows.
+* ``kkt_points_general``: the same for rows rl <= A x <= ru given on the
+  caller's rows (upper-bound and two-sided rows included), enumerating each
+  row's activity at its lower or upper bound.
 """
 
 import itertools
@@ -120,4 +123,71 @@ def kkt_points(Q, c, AE, bE, AI, bI, xl, xu, tol=1e-9):
             if np.any(g[xa == -1] < -tol) or np.any(g[xa == 1] > tol):
                 continue
             out.append((x, lamE, lamI))
+    return out
+
+
+def kkt_points_general(Q, c, A, rl, ru, xl, xu, tol=1e-9):
+    """All KKT points (x, lam) of a tiny QP with general rows
+    rl <= A x <= ru (rl == ru an equality), in the sign convention
+    Qx + c + A'lam + N_[xl,xu](x) contains 0: lam_j <= 0 when row j sits at
+    its lower bound, >= 0 at its upper bound, free on an equality row, 0 on
+    an inactive row.  Enumerates bound activity of every variable and every
+    row directly on the caller's rows (no conversion to another form)."""
+    n = Q.shape[0]
+    m = A.shape[0]
+    out = []
+    row_states = []
+    for j in range(m):
+        if rl[j] == ru[j]:
+            row_states.append((2,))          # equality: always active
+        else:
+            st = [0]
+            if np.isfinite(rl[j]):
+                st.append(-1)
+            if np.isfinite(ru[j]):
+                st.append(1)
+            row_states.append(tuple(st))
+    for xa in itertools.product((-1, 0, 1), repeat=n):
+        xa = np.array(xa)
+        xfix = np.where(xa == -1, xl, np.where(xa == 1, xu, np.nan))
+        if np.any(~np.isfinite(xfix[xa != 0])):
+            continue
+        for ra in itertools.product(*row_states):
+            ra = np.array(ra, dtype=int)
+            act = np.nonzero(ra != 0)[0]
+            target = np.array([rl[j] if ra[j] in (-1, 2) else ru[j] for j in act])
+            free = np.nonzero(xa == 0)[0]
+            nf, na = free.size, act.size
+            nv = nf + na
+            M = np.zeros((nf + na, nv))
+            rhs = np.zeros(nf + na)
+            fixed = xa != 0
+            for r, i in enumerate(free):
+                M[r, :nf] = Q[i, free]
+                M[r, nf:] = A[act, i]
+                rhs[r] = -(c[i] + Q[i, fixed] @ xfix[fixed])
+            for r, j in enumerate(act):
+                M[nf + r, :nf] = A[j, free]
+                rhs[nf + r] = target[r] - A[j, fixed] @ xfix[fixed]
+            if nv:
+                if abs(np.linalg.det(M)) < 1e-12:
+                    continue
+                sol = np.linalg.solve(M, rhs)
+            else:
+                sol = np.zeros(0)
+            x = xfix.copy()
+            x[free] = sol[:nf]
+            lam = np.zeros(m)
+            lam[act] = sol[nf:]
+            if np.any(x < xl - tol) or np.any(x > xu + tol):
+                continue
+            ax = A @ x
+            if np.any(ax < rl - tol) or np.any(ax > ru + tol):
+                continue
+            if np.any((ra == -1) & (lam > tol)) or np.any((ra == 1) & (lam < -tol)):
+                continue
+            g = Q @ x + c + A.T @ lam
+            if np.any(g[xa == -1] < -tol) or np.any(g[xa == 1] > tol):
+                continue
+            out.append((x, lam))
     return out
