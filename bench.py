@@ -58,11 +58,27 @@ def _describe(prob):
             f"(half equalities), nnz(Q)={prob['Q'].nnz:,}, nnz(A)={prob['A'].nnz:,}, box [0,1]")
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, n_inner):
     """FP64 CPU oracle on a bounded sample of the same instance: one outer
-    step whose inner solve is capped at ``n_inner`` accepted iterations.
-    The rate counts only the time spent inside the oracle's inner solver
-    (its set-up -- scaling, Lanczos, inner-QP formation -- is excluded)."""
+    step whose inner solve is capped at ``n_inner`` accepted iterations
+    (checks after every 64).  The rate counts only the time spent inside the
+    oracle's inner solver (its set-up -- scaling, Lanczos, inner-QP
+    formation -- is excluded).  The oracle runs on one core: every BLAS/
+    OpenMP thread pool is limited to one thread for the whole leg (scipy's
+    sparse products are single-threaded)."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import pdnqp_oracle as O
     spent = [0.0]
     orig = O.inner_solve
@@ -75,20 +91,25 @@ def cpu_baseline(prob, n_inner):
 
     O.inner_solve = timed
     try:
-        st = O.Settings(max_outer=1, max_inner=n_inner)
-        t0 = time.perf_counter()
-        r = O.solve(prob, st)
-        total = time.perf_counter() - t0
+        with threadpool_limits(limits=1):
+            st = O.Settings(max_outer=1, max_inner=n_inner)
+            t0 = time.perf_counter()
+            r = O.solve(prob, st)
+            total = time.perf_counter() - t0
     finally:
         O.inner_solve = orig
     rate = r.counters.accepted / max(1e-9, spent[0])
-    threads = os.environ.get("OMP_NUM_THREADS", "unset")
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
     return {"value": round(rate, 3), "unit": "inner iters/s", "cores": 1, "kind": "oracle",
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(), "host_cpus_available": avail,
             "sample": (f"one outer step of the same n={prob['n']:,} instance with the inner "
-                       f"solve capped at {r.counters.accepted} accepted iterations; "
+                       f"solve capped at {r.counters.accepted} accepted iterations "
+                       f"({r.counters.accepted // 64} stopping/restart checks); "
                        f"{spent[0]:.1f} s inside the inner solver ({total:.1f} s with the "
-                       f"oracle's set-up); numpy/scipy FP64, single thread for the sparse "
-                       f"products (OMP_NUM_THREADS={threads})")}
+                       f"oracle's set-up); numpy/scipy FP64 on one thread")}
 
 
 def batch_leg(P, qpgen, args):
@@ -155,11 +176,12 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--cpu-iters", type=int, default=256)
     ap.add_argument("--tol-time-limit", type=float, default=90.0)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32",
-                    help="fp32: FP32 matrix values and inner vectors with FP64 reductions, FP64 "
-                         "outer update and final check (the large workload's stated arithmetic)")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="fp64 (the paper's arithmetic, default); fp32: FP32 matrix values and "
+                         "inner vectors with FP64 reductions, FP64 outer update and final check "
+                         "(the FP32-bulk extension, also timed as the other-precision leg)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (512 uneven instances, one persistent launch)")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -170,8 +192,6 @@ def main():
                          "(0: none)")
     ap.add_argument("--no-other-precision", action="store_true",
                     help="skip timing the other precision on the same instance")
-    ap.add_argument("--no-flow", action="store_true",
-                    help="skip the time to 1e-4 on the n ~ 1M flow-family stand-in")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -258,29 +278,6 @@ def main():
         st.close()
         print(f"[bench] time-to-1e-4: {ttt}", file=sys.stderr, flush=True)
 
-    # time to 1e-4 at n ~ 1M on the flow-family stand-in (concave-cost
-    # multistage flow), from its feasible reference flow, in both precisions
-    flow = None
-    if not args.no_flow:
-        fp = qpgen.flow_qp(101)
-        flow = {"workload": f"flow-family stand-in (concave-cost multistage flow, seed 101): "
-                            f"n={fp['n']:,} arcs, m={fp['m']:,} node rows, {fp['layers']} layers",
-                "tol": 1e-4, "start": "feasible reference flow", "outer_scaling": "ruiz_a (paper)"}
-        for pname, pr in (("fp64", P.FP64), ("fp32", P.FP32)):
-            sf = P.Solver.from_problem(fp, use_torch=True, time_limit_s=60.0, precision=pr)
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            _, _, inf3 = sf.solve(1e-4, 1e-4, x0=fp["x0"])
-            torch.cuda.synchronize()
-            flow[pname] = {"seconds": round(time.perf_counter() - t3, 3),
-                           "status": inf3["status_name"], "outer_iters": inf3["outer_iters"],
-                           "inner_accepted": inf3["inner_accepted"], "r_p": inf3["r_p"],
-                           "r_d": inf3["r_d"], "s_p": inf3["s_p"], "s_d": inf3["s_d"],
-                           "promoted_outer": inf3["promoted_outer"]}
-            sf.close()
-        del fp
-        print(f"[bench] flow time-to-1e-4: {flow}", file=sys.stderr, flush=True)
-
     other = None
     if not args.no_other_precision:
         oprec = P.FP64 if args.precision == "fp32" else P.FP32
@@ -335,7 +332,6 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_tol": ttt,
-        "time_to_tol_flow": flow,
         "other_precision": other,
         "batch": batch,
         "trial": {"us_per_trial_kernels": round(trial_us, 3),

@@ -51,7 +51,12 @@ enum {
   PDNQP_SOLVED = 1,
   PDNQP_MAX_ITER = 2,
   PDNQP_TIME_LIMIT = 3,
-  PDNQP_NUMERICAL_ERROR = 4
+  PDNQP_NUMERICAL_ERROR = 4,
+  /* The scaled test passed at the smallest internal tolerances of the
+   * calibration (settings.external_halvings) but the KKT test on the
+   * caller's unscaled problem did not (Section 4, termination and tolerance
+   * calibration: such a point counts as a failure). */
+  PDNQP_INACCURATE = 5
 };
 
 /* Outer scaling modes (Section 3.1, eq. (scaled-problem)). */
@@ -132,19 +137,32 @@ typedef struct pdnqp_settings {
                               runs the FP64 inner iteration (FP32 storage bounds the inner
                               residual it can reach); 1e-5 (default); 0: never */
   double delta_floor;      /* [reading] the inner tolerances never fall below delta_floor times
-                              eps_abs, eps_rel (inner-tolerance-factor states no floor); 1 */
+                              eps_abs, eps_rel (inner-tolerance-factor states no floor); 1;
+                              0: no floor (the paper's rule as stated) */
   int32_t fp32_stall;      /* with PDNQP_FP32: after this many outer steps without a 10% gain of
                               the outer KKT measure max(r_p/(eps_abs+eps_rel s_p),
                               r_d/(eps_abs+eps_rel s_d)), the rest of the solve runs the FP64 inner
                               iteration (FP32 rounding of the iterate can stall the outer
                               iteration above the tolerance); 50 (default); 0: never */
-  int32_t reserved_s;
+  int32_t external_halvings; /* [reading] the experimental protocol's tolerance calibration,
+                              run as a continuation (Section 4, termination and tolerance
+                              calibration): when the scaled test (outer-termination) passes
+                              but the same test on the caller's unscaled problem (primal
+                              residual with bound violation, projected stationarity) does
+                              not, every internal use of eps_abs, eps_rel (scaled test,
+                              penalty gate, inner-tolerance and centre floors, Anderson) is
+                              halved and the outer iteration continues; after this many
+                              halvings such a point ends the solve with PDNQP_INACCURATE.
+                              7 (default: 1/128, the protocol's limit); 0: stop on the
+                              scaled test alone */
   void *hip_stream;        /* hipStream_t to run on; NULL: the library creates its own */
   /* Device memory provider.  NULL: hipMalloc/hipFree.  Called only from
    * pdnqp_create / pdnqp_destroy (and pdnqp_solve when tracing). */
   void *(*dev_alloc)(size_t bytes, void *user);
   void (*dev_free)(void *ptr, void *user);
   void *alloc_user;
+  double delta0;           /* [paper] initial inner tolerances delta_{a,0} = delta_{r,0}, 1
+                              (Section 3.1, outer-loop initialization) */
 } pdnqp_settings;
 
 /* Per-solve report. */
@@ -174,7 +192,8 @@ typedef struct pdnqp_info {
   int32_t outer_logged;    /* outer steps recorded for pdnqp_get_outer_log */
   int32_t promoted_outer;  /* with PDNQP_FP32: the outer step from which the inner iteration ran
                               in FP64 (settings.fp32_promote); 0: none */
-  int32_t reserved2;
+  int32_t halvings;        /* internal tolerance halvings taken by the calibration
+                              (settings.external_halvings) */
 } pdnqp_info;
 
 /* Writes the defaults into *s.  Never fails. */

@@ -55,6 +55,9 @@ SOLVED = 1
 MAX_ITER = 2
 TIME_LIMIT = 3
 NUMERICAL_ERROR = 4
+# the scaled test passed at the smallest internal tolerances of the
+# calibration but the external test on the unscaled problem did not
+INACCURATE = 5
 
 INNER_CONVERGED = 0
 INNER_ITER_LIMIT = 1
@@ -77,6 +80,8 @@ class Settings:
     rho_in_max: float = 0.95
     rho_z: float = 0.95
     ruiz_sweeps: int = 8
+    # initial inner tolerances delta_{a,0} = delta_{r,0} (the paper: 1)
+    delta0: float = 1.0
     # [reading] restart cadence and thresholds (PDLP-style KKT restarts)
     check_every: int = 64
     restart_suff: float = 0.2
@@ -115,6 +120,13 @@ class Settings:
     # [reading] Tikhonov weight of the Anderson least-squares problem,
     # relative to the mean diagonal of its Gram matrix
     anderson_reg: float = 1e-10
+    # [reading] the experimental protocol's tolerance calibration, run as a
+    # continuation: when the scaled test (outer-termination) passes but the
+    # external test on the unscaled problem does not, every internal use of
+    # eps_abs, eps_rel is halved and the outer iteration goes on, at most
+    # this many times (1/128 of the requested tolerances); 0: stop on the
+    # scaled test alone
+    external_halvings: int = 7
 
 
 # ---------------------------------------------------------------------------
@@ -533,6 +545,9 @@ class Trace:
     # of the penalty, inner-tolerance and centre rules
     max_rules: int = 0
     rules: list = field(default_factory=list)
+    # (k, internal eps_abs, eps_rel, unscaled r_p, r_d, s_p, s_d) at every
+    # outer step whose scaled test passed
+    external: list = field(default_factory=list)
 
 
 @dataclass
@@ -767,18 +782,19 @@ def inner_tolerance_factor(x_new, z, gamma, r_d, st: Settings):
     return st.rho_in_max - (st.rho_in_max - st.rho_in_min) * ratio
 
 
-def center_update(x_new, z, r_p, s_p, eps_ak, eps_rk, st: Settings):
+def center_update(x_new, z, r_p, s_p, eps_ak, eps_rk, st: Settings, floor=None):
     """eq. (center-update) and (center-tolerance-update): the centre moves to
     x^{k+1} exactly when r_p <= eps_{a,k} + eps_{r,k} s_p, and after such a
     move both centre tolerances are multiplied by rho_z.  [reading] with
-    ``st.center_floor`` they are floored at the outer tolerances.  Returns
-    (z, eps_a, eps_r, moved)."""
+    ``st.center_floor`` they are floored at the outer tolerances (``floor``,
+    default (eps_abs, eps_rel)).  Returns (z, eps_a, eps_r, moved)."""
     if r_p <= eps_ak + eps_rk * s_p:
         eps_ak *= st.rho_z
         eps_rk *= st.rho_z
         if st.center_floor:
-            eps_ak = max(eps_ak, st.eps_abs)
-            eps_rk = max(eps_rk, st.eps_rel)
+            fa, fr = floor if floor is not None else (st.eps_abs, st.eps_rel)
+            eps_ak = max(eps_ak, fa)
+            eps_rk = max(eps_rk, fr)
         return x_new.copy(), eps_ak, eps_rk, True
     return z, eps_ak, eps_rk, False
 
@@ -802,6 +818,7 @@ class Result:
     sigma: np.ndarray = None
     omega: float = math.nan
     anderson_steps: int = 0
+    halvings: int = 0
 
 
 def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
@@ -827,7 +844,8 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
     z = x.copy()
     lam = S.c_obj * lam_int / S.Dc
     sigma = initial_penalty(S, x, st)
-    delta_a = delta_r = eps_ak = eps_rk = 1.0
+    delta_a = delta_r = st.delta0
+    eps_ak = eps_rk = 1.0
     omega = st.omega0
     y = -lam.copy()               # [reading] inner dual starts at -lambda
     r_prev = None
@@ -836,6 +854,8 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
     status = MAX_ITER
     k = 0
     rp = rd = sp_ = sd = math.nan
+    ea, er = st.eps_abs, st.eps_rel   # internal tolerances (halved by the calibration)
+    halvings = 0
     aa_u, aa_g = [], []       # Anderson history: points and their images
     aa_last = None            # residuals at the last extrapolation
     aa_steps = 0
@@ -871,10 +891,27 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
         rp, rd, sp_, sd = outer_residuals(S, x_new, lam)
         if trace is not None:
             trace.outer.append((k, rp, rd, sp_, sd))
-        if rp <= st.eps_abs + st.eps_rel * sp_ and rd <= st.eps_abs + st.eps_rel * sd:
-            x = x_new
-            status = SOLVED
-            break
+        if rp <= ea + er * sp_ and rd <= ea + er * sd:
+            # [reading] accepted only when the external test on the unscaled
+            # problem passes too (the experimental protocol), else the
+            # internal tolerances are halved and the iteration goes on
+            x_u, lam_u = unscale(P, S, x_new, lam, prob["A"].shape[0])
+            ext = external_kkt(prob, x_u, lam_u)
+            if trace is not None:
+                trace.external.append((k, ea, er) + tuple(ext))
+            if (st.external_halvings == 0 or
+                    (ext[0] <= st.eps_abs + st.eps_rel * ext[2] and
+                     ext[1] <= st.eps_abs + st.eps_rel * ext[3])):
+                x = x_new
+                status = SOLVED
+                break
+            if halvings >= st.external_halvings:
+                x = x_new
+                status = INACCURATE
+                break
+            halvings += 1
+            ea *= 0.5
+            er *= 0.5
         # row-wise penalty update, eq. (penalty-trigger-eq); [reading] the
         # first update is skipped (no previous residual yet)
         r_row = np.concatenate([ax[:me] - S.b[:me], ax[me:] - s_new])
@@ -882,17 +919,18 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
         active = np.concatenate([np.ones(me, bool), lam[me:] < 0.0])
         if r_prev is not None:
             sigma, _ = penalty_update(sigma, r_row, r_prev, active,
-                                      st.eps_abs + st.eps_rel * sp_, st)
+                                      ea + er * sp_, st)
         penalties_moved = bool(np.any(sigma != sigma_before))
         # eq. (inner-tolerance-factor); [reading] the inner tolerances are
         # floored at delta_floor times the outer tolerances
         rho = inner_tolerance_factor(x_new, z, gamma, rd, st)
-        delta_a = max(st.delta_floor * st.eps_abs, rho * delta_a)
-        delta_r = max(st.delta_floor * st.eps_rel, rho * delta_r)
+        delta_a = max(st.delta_floor * ea, rho * delta_a)
+        delta_r = max(st.delta_floor * er, rho * delta_r)
         # eq. (center-update) / (center-tolerance-update)
         eps_before = (eps_ak, eps_rk)
         z_old = z
-        z, eps_ak, eps_rk, moved = center_update(x_new, z, rp, sp_, eps_ak, eps_rk, st)
+        z, eps_ak, eps_rk, moved = center_update(x_new, z, rp, sp_, eps_ak, eps_rk, st,
+                                                 floor=(ea, er))
         if trace is not None and len(trace.rules) < trace.max_rules:
             trace.rules.append(dict(
                 k=k, rp=rp, rd=rd, sp=sp_, sd=sd, x=x_new.copy(), z_old=z_old.copy(),
@@ -904,8 +942,9 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
         r_prev = r_row
         # Anderson step on (lambda_E, lambda_I, z), Section 3.2
         if st.anderson_mem > 0:
-            lam, z, aa_last = _anderson_outer(st, S, me, u_form, lam, z, rp, rd, sp_,
-                                              penalties_moved, aa_u, aa_g, aa_last, rd_prev)
+            lam, z, aa_last = _anderson_outer(st, S, me, u_form, lam, z, rp, rd,
+                                              ea + er * sp_, penalties_moved, aa_u, aa_g,
+                                              aa_last, rd_prev)
             aa_steps += aa_last is not None
             if aa_last is not None:
                 # [reading] the inner dual warm start follows the extrapolated
@@ -917,23 +956,31 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
         if time.monotonic() > deadline:
             status = TIME_LIMIT
             break
-    # unscale (Section 3.1) and map back to the caller's rows
-    x_orig = np.clip(S.Dx * x, P.xl, P.xu)   # unscaling may step an ulp outside the box
+    x_orig, lam_out = unscale(P, S, x, lam, prob["A"].shape[0])
     lam_scaled_int = lam
-    lam_int_orig = S.Dc * lam / S.c_obj
-    lam_out = np.zeros(prob["A"].shape[0])
-    np.add.at(lam_out, P.row_of, P.sign_of * lam_int_orig)
     res = Result(status=status, x=x_orig, lam=lam_out, outer_iters=k, counters=cnt,
                  gamma=gamma, lambda_hat=lam_hat, scaled_x=x, scaled_lam=lam_scaled_int,
                  sigma=sigma, omega=omega)
     res.anderson_steps = aa_steps
+    res.halvings = halvings
     res.r_p, res.r_d, res.s_p, res.s_d = external_kkt(prob, x_orig, lam_out)
     Qo = sp.csr_matrix(prob["Q"])
     res.objective = 0.5 * float(x_orig @ (Qo @ x_orig)) + float(np.asarray(prob["c"]) @ x_orig)
     return res
 
 
-def _anderson_outer(st, S, me, u_form, lam, z, rp, rd, sp_, penalties_moved, aa_u, aa_g,
+def unscale(P: Normalised, S: Scaled, x, lam, m_orig):
+    """Section 3.1: x = D_x x_bar, lambda = D_c lambda_bar / c_obj, then the
+    internal rows' multipliers mapped back to the caller's rows (with the
+    sign of each row's normalisation; the two rows of a two-sided row add
+    up).  x is clipped into the box, which unscaling may leave by an ulp."""
+    x_orig = np.clip(S.Dx * x, P.xl, P.xu)
+    lam_out = np.zeros(m_orig)
+    np.add.at(lam_out, P.row_of, P.sign_of * (S.Dc * lam / S.c_obj))
+    return x_orig, lam_out
+
+
+def _anderson_outer(st, S, me, u_form, lam, z, rp, rd, tol_p, penalties_moved, aa_u, aa_g,
                     aa_last, rd_prev):
     """One outer step's Anderson bookkeeping.  [reading] The paper applies
     the step once primal feasibility is reached and the row penalties are
@@ -955,7 +1002,7 @@ def _anderson_outer(st, S, me, u_form, lam, z, rp, rd, sp_, penalties_moved, aa_
         aa_u.clear()
         aa_g.clear()
     contracting = rd_prev is not None and rd < rd_prev
-    if not (rp <= st.eps_abs + st.eps_rel * sp_) or penalties_moved or not contracting:
+    if not (rp <= tol_p) or penalties_moved or not contracting:
         aa_u.clear()
         aa_g.clear()
         return lam, z, None

@@ -130,6 +130,8 @@ void pdnqp_default_settings(pdnqp_settings *s) {
   s->fp32_promote = 1e-5;
   s->delta_floor = 1.0;
   s->fp32_stall = 50;
+  s->external_halvings = 7;
+  s->delta0 = 1.0;
 }
 
 size_t pdnqp_settings_size(void) { return sizeof(pdnqp_settings); }
@@ -158,7 +160,9 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         (st.graph != 0 && st.graph != 1) || st.anderson_mem < 0 ||
         st.anderson_mem > PDNQP_ANDERSON_MAX || !(st.anderson_reg >= 0) ||
         (st.controller != 0 && st.controller != 1) || st.outer_log < 0 ||
-        !(st.fp32_promote >= 0) || !(st.delta_floor > 0) || !std::isfinite(st.delta_floor) || st.fp32_stall < 0)
+        !(st.fp32_promote >= 0) || !(st.delta_floor >= 0) || !std::isfinite(st.delta_floor) ||
+        st.fp32_stall < 0 || st.external_halvings < 0 || st.external_halvings > 30 ||
+        !(st.delta0 > 0) || !std::isfinite(st.delta0))
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);

@@ -1387,19 +1387,27 @@ struct BSolver {
     }
   }
 
-  // multiplier update and outer residuals (o: eight maxima)
-  __device__ __forceinline__ void outer_update(double (&o)[8]) {
+  // multiplier update and outer residuals (o: twelve maxima).  o[0..7] on
+  // the scaled data: r_p part, |A_E x|, |A_I x|, |r_row|, r_d, |Q x|,
+  // |A' lambda|, |x - z|.  o[8..11] on the caller's data for the external
+  // test of the experimental protocol: r_p part, max(|A x|, |b|), r_d,
+  // max(|Q x|, |c|, |A' lambda|), with (A x)_j = (bar A bar x)_j / D_c,j,
+  // x = D_x bar x clipped into the caller's box, Q x and A' lambda divided by
+  // c_obj D_x.
+  __device__ __forceinline__ void outer_update(double (&o)[12], double c_obj) {
     const int cur = c.cur;
     const gp<const double> x = G(I.v.X[cur]);
-    for (int k = 0; k < 8; ++k) o[k] = 0.0;
+    for (int k = 0; k < 12; ++k) o[k] = 0.0;
     if (m) {
       const gp<double> ax = G(I.v.ax), lam = G(I.v.lam), rrow = G(I.v.rrow);
-      const gp<const double> b = G(I.b), sig = G(I.v.sigma);
+      const gp<const double> b = G(I.b), sig = G(I.v.sigma), Dc = G(I.v.Dc), br = G(I.braw);
       spmv64(I.A, I.Av, x, [&](int j, double axj) {
         ax[j] = axj;
         const double bj = b[j];
         const double sg = sig[j];
         const double lm = lam[j];
+        const double axr = axj / Dc[j];
+        const double brj = br[j];
         double rr;
         if (j < me) {
           const double res = axj - bj;
@@ -1407,6 +1415,7 @@ struct BSolver {
           rr = res;
           o[0] = fmax(o[0], fabs(res));
           o[1] = fmax(o[1], fabs(axj));
+          o[8] = fmax(o[8], fabs(axr - brj));
         } else {
           const double s = maxv<double>(axj + lm / sg, bj);
           const double ln = lm + sg * (axj - bj);
@@ -1414,15 +1423,18 @@ struct BSolver {
           rr = axj - s;
           o[0] = fmax(o[0], maxv<double>(bj - axj, 0.0));
           o[2] = fmax(o[2], fabs(axj));
+          o[8] = fmax(o[8], maxv<double>(brj - axr, 0.0));
         }
         rrow[j] = rr;
         o[3] = fmax(o[3], fabs(rr));
+        o[9] = fmax(o[9], fmax(fabs(axr), fabs(brj)));
       });
     }
     const gp<double> qxo = G(I.v.qxo), atl = G(I.v.atl);
     spmv64(I.Q, I.Qv, x, [&](int i, double s) { qxo[i] = s; });
     spmv64(I.AT, I.ATv, G(I.v.lam), [&](int i, double s) { atl[i] = s; });
     const gp<const double> cc = G(I.c), lo = G(I.lo), hi = G(I.hi), z = G(I.v.z);
+    const gp<const double> Dx = G(I.v.Dx), cr = G(I.craw), xlr = G(I.xlraw), xur = G(I.xuraw);
     elems(n, [&](int i) {
       const double xv = x[i];
       const double qx = qxo[i], al = atl[i];
@@ -1431,8 +1443,16 @@ struct BSolver {
       o[5] = fmax(o[5], fabs(qx));
       o[6] = fmax(o[6], fabs(al));
       o[7] = fmax(o[7], fabs(xv - z[i]));
+      const double dx = Dx[i];
+      const double sc = 1.0 / (c_obj * dx);
+      const double xl = xlr[i], xu = xur[i];
+      const double xr = clampv<double>(dx * xv, xl, xu);
+      const double qr = qx * sc, ar = al * sc, ci = cr[i];
+      const double prr = clampv<double>(xr - qr - ci - ar, xl, xu);
+      o[10] = fmax(o[10], fabs(xr - prr));
+      o[11] = fmax(o[11], fmax(fmax(fabs(qr), fabs(ci)), fabs(ar)));
     });
-    allreduce<8>(o, 0xFFu);
+    allreduce<12>(o, 0xFFFu);
   }
 
   // row penalties (penalty-trigger-eq); returns whether a penalty changed
@@ -1498,14 +1518,14 @@ struct BSolver {
     aa_pack(I.AU + (size_t)slot * (n + m));
   }
 
-  __device__ __forceinline__ void aa_step(AAState &a, double rp, double rd, double sp,
+  __device__ __forceinline__ void aa_step(AAState &a, double rp, double rd, double tol_p,
                                           double rd_prev, bool moved) {
     const int mem = uni(I.st.anderson_mem);
     const size_t len = (size_t)n + m;
     if (a.last_valid && (rp > a.last_rp || rd > a.last_rd)) a.count = 0;
     a.last_valid = false;
     const bool contracting = rd < rd_prev;
-    if (!(rp <= I.eps_abs + I.eps_rel * sp) || moved || !contracting) {
+    if (!(rp <= tol_p) || moved || !contracting) {
       a.count = 0;
       return;
     }
@@ -1648,9 +1668,13 @@ struct BSolver {
     gamma_inv = 1.0 / gamma;
     h_norm = bE;
     const double eps_abs = I.eps_abs, eps_rel = I.eps_rel;
+    // internal tolerances, halved by the calibration of the external test
+    double ea = eps_abs, er = eps_rel;
+    int32_t halvings = 0;
+    const int32_t max_halvings = uni(I.st.external_halvings);
     double eps_ak = 1.0, eps_rk = 1.0;
-    delta_a = 1.0;
-    delta_r = 1.0;
+    delta_a = I.st.delta0;
+    delta_r = I.st.delta0;
     bool have_prev = false, need_form = true;
     int status = PDNQP_MAX_ITER;
     int64_t k = 0;
@@ -1697,25 +1721,39 @@ struct BSolver {
         }
         continue;
       }
-      double o[8];
-      outer_update(o);
+      double o[12];
+      outer_update(o, c_obj);
       rp = m ? o[0] : 0.0;
       sp = fmax(fmax(fmax(1.0, m ? o[1] : 0.0), fmax(bE, m ? o[2] : 0.0)), bI);
       rd = o[4];
       sd = fmax(fmax(1.0, o[5]), fmax(cn, o[6]));
       const double dxz = o[7];
       const double rn = m ? o[3] : 0.0;
-      if (rp <= eps_abs + eps_rel * sp && rd <= eps_abs + eps_rel * sd) {
-        status = PDNQP_SOLVED;
-        break;
+      if (rp <= ea + er * sp && rd <= ea + er * sd) {
+        // external test on the caller's data; on failure the internal
+        // tolerances are halved and the iteration continues
+        const double rpu = m ? o[8] : 0.0, spu = fmax(1.0, m ? o[9] : 0.0);
+        const double rdu = o[10], sdu = fmax(1.0, o[11]);
+        if (max_halvings == 0 ||
+            (rpu <= eps_abs + eps_rel * spu && rdu <= eps_abs + eps_rel * sdu)) {
+          status = PDNQP_SOLVED;
+          break;
+        }
+        if (halvings >= max_halvings) {
+          status = PDNQP_INACCURATE;
+          break;
+        }
+        halvings += 1;
+        ea *= 0.5;
+        er *= 0.5;
       }
-      const bool moved = penalties(have_prev, rn, eps_abs + eps_rel * sp);
+      const bool moved = penalties(have_prev, rn, ea + er * sp);
       have_prev = true;
       // inner tolerances (inner-tolerance-factor)
       const double ratio = (rd == 0.0) ? 1.0 : fmin(1.0, dxz / gamma / rd);
       const double rho = I.st.rho_in_max - (I.st.rho_in_max - I.st.rho_in_min) * ratio;
-      delta_a = fmax(I.st.delta_floor * eps_abs, rho * delta_a);
-      delta_r = fmax(I.st.delta_floor * eps_rel, rho * delta_r);
+      delta_a = fmax(I.st.delta_floor * ea, rho * delta_a);
+      delta_r = fmax(I.st.delta_floor * er, rho * delta_r);
       // proximal centre (center-update)
       if (rp <= eps_ak + eps_rk * sp) {
         const gp<double> z = G(I.v.z);
@@ -1724,12 +1762,12 @@ struct BSolver {
         eps_ak *= I.st.rho_z;
         eps_rk *= I.st.rho_z;
         if (I.st.center_floor) {
-          eps_ak = fmax(eps_ak, eps_abs);
-          eps_rk = fmax(eps_rk, eps_rel);
+          eps_ak = fmax(eps_ak, ea);
+          eps_rk = fmax(eps_rk, er);
         }
       }
       __syncthreads();
-      if (aa_on) aa_step(aa, rp, rd, sp, rd_prev, moved);
+      if (aa_on) aa_step(aa, rp, rd, ea + er * sp, rd_prev, moved);
       rd_prev = rd;
       need_form = true;
       if (clock_now() > deadline) {
@@ -1759,6 +1797,7 @@ struct BSolver {
       o->staged = STAGE ? 1 : 0;
       o->anderson_steps = aa_on ? aa.steps : 0;
       o->outer_iters = k;
+      o->halvings = halvings;
       o->trials = c.trials;
       o->accepted = c.accepted;
       o->rejected = c.rejected;

@@ -30,7 +30,7 @@ struct BatchOut {
   int32_t trace_iters_n, trace_trials_n, trace_checks_n;
   int32_t staged;     // 1 when the gathered vectors were staged in LDS
   int32_t anderson_steps;
-  int32_t pad;
+  int32_t halvings;   // internal tolerance halvings of the external-test calibration
   int64_t outer_iters, trials, accepted, rejected, restarts, checks;
   double rp, rd, sp, sd;  // scaled outer residuals and scales at exit
   double gamma, lam_hat, omega, c_obj;

@@ -173,11 +173,18 @@ __global__ __launch_bounds__(kBlock) void k_warm(InnerParams p, Vecs v, int cur,
 // Outer step (eq. (practical-multiplier-update), (outer-residuals),
 // (outer-scales)).
 // ===========================================================================
+// Multiplier update (practical-multiplier-update) and the row part of the
+// outer residuals (outer-residuals)/(outer-scales), on the scaled data and,
+// for the external test of the experimental protocol, on the caller's data:
+// row j of the unscaled problem reads (A x)_j = (bar A bar x)_j / D_c,j
+// against the raw right-hand side.  outv[0..3]: scaled r_p part, |A_E x|,
+// |A_I x|, |r_row|; outv[8]: unscaled r_p part; outv[9]: max of |A x| and
+// |b| unscaled.
 template <int GA>
 __global__ __launch_bounds__(kBlock) void k_outer_rows(Ctrl *__restrict__ c, InnerParams p,
-                                                       Vecs v, Csr A, Part pa) {
+                                                       Vecs v, Csr A, Part pa, RawData raw) {
   const int cur = c->cur;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};  // r_p part, |A_E x|, |A_I x|, |r_row|
+  double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for_rows<GA>(A.rows, blockIdx.x, gridDim.x, [&](int j, int lane) {
     const double ax = row_dot<GA, double>(A.p, A.i, A.v, v.X[cur], j, lane);
     if (lane == 0) {
@@ -185,6 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_outer_rows(Ctrl *__restrict__ c, Inn
       const double bj = v.b[j];
       const double sg = v.sigma[j];
       const double lm = v.lam[j];
+      const double axr = ax / v.Dc[j];
+      const double br = raw.b[j];
       double rr;
       if (j < p.me) {
         const double res = ax - bj;
@@ -192,6 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_rows(Ctrl *__restrict__ c, Inn
         rr = res;
         a[0] = fmax(a[0], fabs(res));
         a[1] = fmax(a[1], fabs(ax));
+        a[4] = fmax(a[4], fabs(axr - br));
       } else {
         const double s = maxv<double>(ax + lm / sg, bj);
         const double ln = lm + sg * (ax - bj);
@@ -199,27 +209,38 @@ __global__ __launch_bounds__(kBlock) void k_outer_rows(Ctrl *__restrict__ c, Inn
         rr = ax - s;
         a[0] = fmax(a[0], maxv<double>(bj - ax, 0.0));
         a[2] = fmax(a[2], fabs(ax));
+        a[4] = fmax(a[4], maxv<double>(br - axr, 0.0));
       }
       v.rrow[j] = rr;
       a[3] = fmax(a[3], fabs(rr));
+      a[5] = fmax(a[5], fmax(fabs(axr), fabs(br)));
     }
   });
-  block_reduce<4>(a, 0xFu, v.partial, blockIdx.x);
+  block_reduce<6>(a, 0x3Fu, v.partial, blockIdx.x);
   if (last_block(&c->ticket[TK_OUTER_ROWS], gridDim.x)) {
-    double r[4];
-    final_reduce<4>(v.partial, gridDim.x, 0xFu, r);
+    double r[6];
+    final_reduce<6>(v.partial, gridDim.x, 0x3Fu, r);
     if (threadIdx.x == 0) {
       for (int k = 0; k < 4; ++k) c->outv[k] = r[k];
+      c->outv[8] = r[4];
+      c->outv[9] = r[5];
       c->ticket[TK_OUTER_ROWS] = 0;
     }
   }
 }
 
+// Column part of the outer residuals: projected stationarity and its scale
+// on the scaled data (outv[4..7]: r_d, |Q x|, |A' lambda|, |x - z|) and on
+// the caller's data (outv[10]: unscaled r_d; outv[11]: max of |Q x|, |c|,
+// |A' lambda| unscaled), with x = D_x bar x clipped into the caller's box,
+// Q x = (bar Q bar x) / (c_obj D_x), A' lambda = (bar A' bar lambda) /
+// (c_obj D_x).
 template <int GQ, int GT>
 __global__ __launch_bounds__(kBlock) void k_outer_cols(Ctrl *__restrict__ c, InnerParams p,
-                                                       Vecs v, Csr Q, Csr AT, Part pq) {
+                                                       Vecs v, Csr Q, Csr AT, Part pq,
+                                                       RawData raw) {
   const int cur = c->cur;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};  // r_d, |Q x|, |A' lambda|, |x - z|
+  double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for_rows<GQ>(Q.rows, blockIdx.x, gridDim.x, [&](int i, int lane) {
     const double qx = row_dot<GQ, double>(Q.p, Q.i, Q.v, v.X[cur], i, lane);
     const double atl = row_dot<GT, double>(AT.p, AT.i, AT.v, v.lam, i, lane);
@@ -232,14 +253,24 @@ __global__ __launch_bounds__(kBlock) void k_outer_cols(Ctrl *__restrict__ c, Inn
       a[3] = fmax(a[3], fabs(x - v.z[i]));
       v.qxo[i] = qx;
       v.atl[i] = atl;
+      const double dx = v.Dx[i];
+      const double sc = 1.0 / (raw.c_obj * dx);
+      const double xl = raw.xl[i], xu = raw.xu[i];
+      const double xr = clampv<double>(dx * x, xl, xu);
+      const double qr = qx * sc, ar = atl * sc, cr = raw.c[i];
+      const double prr = clampv<double>(xr - qr - cr - ar, xl, xu);
+      a[4] = fmax(a[4], fabs(xr - prr));
+      a[5] = fmax(a[5], fmax(fmax(fabs(qr), fabs(cr)), fabs(ar)));
     }
   });
-  block_reduce<4>(a, 0xFu, v.partial, blockIdx.x);
+  block_reduce<6>(a, 0x3Fu, v.partial, blockIdx.x);
   if (last_block(&c->ticket[TK_OUTER_COLS], gridDim.x)) {
-    double r[4];
-    final_reduce<4>(v.partial, gridDim.x, 0xFu, r);
+    double r[6];
+    final_reduce<6>(v.partial, gridDim.x, 0x3Fu, r);
     if (threadIdx.x == 0) {
       for (int k = 0; k < 4; ++k) c->outv[4 + k] = r[k];
+      c->outv[10] = r[4];
+      c->outv[11] = r[5];
       c->ticket[TK_OUTER_COLS] = 0;
     }
   }
@@ -636,20 +667,20 @@ void launch_viol(hipStream_t st, const InnerParams &p, const Vecs &v, double *ou
 }
 
 void launch_outer_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
-                       const Csr &A, const Part &pa) {
+                       const Csr &A, const Part &pa, const RawData &raw) {
   PDNQP_DISPATCH_G(A.G, {
     hipLaunchKernelGGL((k_outer_rows<GV>), dim3(nz(pa.blocks)), dim3(kBlock), 0, st, c, p, v, A,
-                       pa);
+                       pa, raw);
   });
 }
 
 void launch_outer_cols(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
-                       const Csr &Q, const Csr &AT, const Part &pq) {
+                       const Csr &Q, const Csr &AT, const Part &pq, const RawData &raw) {
   const int G = Q.G > AT.G ? Q.G : AT.G;
   Part pqq = make_part(Q.rows, G, 1024);
   PDNQP_DISPATCH_G(G, {
     hipLaunchKernelGGL((k_outer_cols<GV, GV>), dim3(nz(pqq.blocks)), dim3(kBlock), 0, st, c, p, v,
-                       Q, AT, pqq);
+                       Q, AT, pqq, raw);
   });
   (void)pq;
 }

@@ -221,10 +221,17 @@ void launch_steps(hipStream_t st, const InnerParams &p, const Vecs &v, const Csr
 void launch_warm(hipStream_t st, const InnerParams &p, const Vecs &v, int cur, double gamma);
 
 // ---- outer step --------------------------------------------------------------
+// The caller's (unscaled) data in internal row order, for the external KKT
+// test inside the outer loop: right-hand sides b, variable bounds, linear
+// term, and the objective scalar of the outer scaling.
+struct RawData {
+  const double *b, *xl, *xu, *c;
+  double c_obj;
+};
 void launch_outer_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
-                       const Csr &A, const Part &pa);
+                       const Csr &A, const Part &pa, const RawData &raw);
 void launch_outer_cols(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
-                       const Csr &Q, const Csr &AT, const Part &pq);
+                       const Csr &Q, const Csr &AT, const Part &pq, const RawData &raw);
 void launch_penalty(hipStream_t st, Ctrl *c, const InnerParams &p, const Vecs &v,
                     const Part &pr, int have_prev, double rnorm, double theta, double growth,
                     double sig_max, int gate, double gate_tol);

@@ -744,7 +744,12 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   ip_.restart_art = st_.restart_art;
   ip_.mode_init = 0;
 
-  double delta_a = 1.0, delta_r = 1.0, eps_ak = 1.0, eps_rk = 1.0;
+  double delta_a = st_.delta0, delta_r = st_.delta0, eps_ak = 1.0, eps_rk = 1.0;
+  // internal tolerances: the requested ones, halved by the calibration of
+  // the external test (reading of the experimental protocol)
+  double ea = eps_abs, er = eps_rel;
+  int32_t halvings = 0;
+  const RawData raw{braw_, xlraw_, xuraw_, craw_, c_obj};
   double rd_prev = NAN;  // r_d of the previous outer step (none yet: not contracting)
   bool have_prev = false, need_form = true;
   int status = PDNQP_MAX_ITER;
@@ -826,8 +831,8 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
       continue;
     }
     // multiplier update and outer residuals
-    if (m) launch_outer_rows(stream_, ctrl_, ip_, v_, A_, pa_);
-    launch_outer_cols(stream_, ctrl_, ip_, v_, Q_, AT_, pq_);
+    if (m) launch_outer_rows(stream_, ctrl_, ip_, v_, A_, pa_, raw);
+    launch_outer_cols(stream_, ctrl_, ip_, v_, Q_, AT_, pq_, raw);
     if ((r = read_ctrl(err))) return r;
     const double *ov = hctrl_->outv;
     rp = m ? ov[0] : 0.0;
@@ -874,9 +879,29 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
                    delta_a, now_s() - t_start);
       std::fflush(stderr);
     }
-    if (rp <= eps_abs + eps_rel * sp && rd <= eps_abs + eps_rel * sd) {
-      status = PDNQP_SOLVED;
-      break;
+    if (rp <= ea + er * sp && rd <= ea + er * sd) {
+      // the external test on the caller's data (experimental protocol):
+      // accepted when it passes too; otherwise every internal use of the
+      // tolerances is halved and the iteration continues, at most
+      // external_halvings times
+      const double rpu = m ? ov[8] : 0.0, spu = std::max(1.0, m ? ov[9] : 0.0);
+      const double rdu = ov[10], sdu = std::max(1.0, ov[11]);
+      if (st_.external_halvings == 0 ||
+          (rpu <= eps_abs + eps_rel * spu && rdu <= eps_abs + eps_rel * sdu)) {
+        status = PDNQP_SOLVED;
+        break;
+      }
+      if (halvings >= st_.external_halvings) {
+        status = PDNQP_INACCURATE;
+        break;
+      }
+      halvings += 1;
+      ea *= 0.5;
+      er *= 0.5;
+      if (st_.verbose)
+        std::fprintf(stderr, "[pdnqp] outer %lld  external test failed (r_p %.3e, r_d %.3e): "
+                     "internal tolerances halved to %.3e, %.3e\n",
+                     (long long)k, rpu, rdu, ea, er);
     }
     // FP32 bulk that no longer improves the outer KKT measure hands the rest
     // of the solve to the FP64 inner iteration (from the next formation)
@@ -897,26 +922,26 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
                      hipMemcpyHostToDevice, stream_);
     }
     launch_penalty(stream_, ctrl_, ip_, v_, pr_, have_prev ? 1 : 0, rn, st_.theta_sigma,
-                   st_.sigma_growth, st_.sigma_max, st_.penalty_gate, eps_abs + eps_rel * sp);
+                   st_.sigma_growth, st_.sigma_max, st_.penalty_gate, ea + er * sp);
     have_prev = true;
     // inner tolerances (inner-tolerance-factor)
     const double ratio = (rd == 0.0) ? 1.0 : std::min(1.0, dxz / gamma / rd);
     const double rho = st_.rho_in_max - (st_.rho_in_max - st_.rho_in_min) * ratio;
-    delta_a = std::max(st_.delta_floor * eps_abs, rho * delta_a);
-    delta_r = std::max(st_.delta_floor * eps_rel, rho * delta_r);
+    delta_a = std::max(st_.delta_floor * ea, rho * delta_a);
+    delta_r = std::max(st_.delta_floor * er, rho * delta_r);
     // proximal centre (center-update)
     if (rp <= eps_ak + eps_rk * sp) {
       launch_copy(stream_, v_.z, v_.X[hctrl_->cur], n);
       eps_ak *= st_.rho_z;
       eps_rk *= st_.rho_z;
       if (st_.center_floor) {
-        eps_ak = std::max(eps_ak, eps_abs);
-        eps_rk = std::max(eps_rk, eps_rel);
+        eps_ak = std::max(eps_ak, ea);
+        eps_rk = std::max(eps_rk, er);
       }
     }
     // Anderson step on (lambda_E, lambda_I, z), Section 3.2
     if (st_.anderson_mem > 0 &&
-        (r = anderson(rp, rd, sp, eps_abs, eps_rel, rd_prev, err)))
+        (r = anderson(rp, rd, sp, ea, er, rd_prev, err)))
       return r;
     // learned controller: next inner tolerance, iteration budget and primal
     // weight; after 3 outer steps without progress of the outer KKT measure
@@ -941,8 +966,8 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
         return std::isfinite(v) ? std::min(std::max(v, lo), hi) : hi;
       };
       const double dl = std::exp(clampd((double)y[0], -60.0, 0.0));
-      delta_a = std::max(st_.delta_floor * eps_abs, dl);
-      delta_r = std::max(st_.delta_floor * eps_rel, dl);
+      delta_a = std::max(st_.delta_floor * ea, dl);
+      delta_r = std::max(st_.delta_floor * er, dl);
       ip_.max_inner = (int32_t)clampd(std::exp(clampd((double)y[1], 0.0, 30.0)),
                                       (double)st_.check_every, (double)st_.max_inner);
       hctrl_->omega = std::exp(clampd((double)y[2], -9.2, 9.2));
@@ -984,6 +1009,7 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
   oc.anderson_steps = aa_steps_;
   oc.controller_fallback = ctl_fallback ? 1 : 0;
   oc.promoted_outer = promoted_outer;
+  oc.halvings = halvings;
   if ((r = finish(oc, x_out, lam_out, info, err))) return r;
   if (info) info->solve_s = now_s() - t_start;
   return PDNQP_OK;
@@ -1048,6 +1074,7 @@ int Solver::finish(const Outcome &oc, double *x_out, double *lam_out, pdnqp_info
     info->controller_fallback = oc.controller_fallback;
     info->outer_logged = log_n_;
     info->promoted_outer = oc.promoted_outer;
+    info->halvings = oc.halvings;
     external_check(xs, lam_orig, info);
   }
   return PDNQP_OK;
@@ -1243,6 +1270,7 @@ int Solver::batch_finish(const BatchOut &o, double ticks_per_s, double *x_out, d
   oc.trace_trials = o.trace_trials_n;
   oc.trace_checks = o.trace_checks_n;
   oc.anderson_steps = o.anderson_steps;
+  oc.halvings = o.halvings;
   gamma_ = o.gamma;
   const int r = finish(oc, x_out, lam_out, info, err);
   if (r) return r;

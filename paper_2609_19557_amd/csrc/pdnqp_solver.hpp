@@ -51,6 +51,7 @@ struct Outcome {
   int32_t anderson_steps = 0;
   int32_t controller_fallback = 0;
   int32_t promoted_outer = 0;
+  int32_t halvings = 0;
 };
 
 class Solver {

@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libpdnqp.so")
 
 OK = 0
 E_INVALID, E_NOMEM, E_DEVICE, E_STATE = -1, -2, -3, -4
-SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR = 1, 2, 3, 4
+SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR, INACCURATE = 1, 2, 3, 4, 5
 STATUS_NAMES = {SOLVED: "solved", MAX_ITER: "max_iter", TIME_LIMIT: "time_limit",
-                NUMERICAL_ERROR: "numerical_error"}
+                NUMERICAL_ERROR: "numerical_error", INACCURATE: "inaccurate"}
 SCALE_RUIZ_A, SCALE_NONE, SCALE_RUIZ_QA = 0, 1, 2
 FP64, FP32 = 0, 1
 
@@ -72,11 +72,12 @@ class Settings(ctypes.Structure):
         ("fp32_promote", ctypes.c_double),
         ("delta_floor", ctypes.c_double),
         ("fp32_stall", ctypes.c_int32),
-        ("reserved_s", ctypes.c_int32),
+        ("external_halvings", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN),
         ("dev_free", _FREE_FN),
         ("alloc_user", ctypes.c_void_p),
+        ("delta0", ctypes.c_double),
     ]
 
 
@@ -107,7 +108,7 @@ class Info(ctypes.Structure):
         ("controller_fallback", ctypes.c_int32),
         ("outer_logged", ctypes.c_int32),
         ("promoted_outer", ctypes.c_int32),
-        ("reserved2", ctypes.c_int32),
+        ("halvings", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -151,8 +151,10 @@ def test_null_handle_calls_are_errors(P):
                                          ("outer_log", -1), ("precision", 3),
                                          ("fp32_promote", -1e-5),
                                          ("fp32_promote", float("nan")),
-                                         ("delta_floor", 0.0), ("delta_floor", float("inf")),
-                                         ("fp32_stall", -1)])
+                                         ("delta_floor", -0.5), ("delta_floor", float("inf")),
+                                         ("fp32_stall", -1), ("external_halvings", -1),
+                                         ("external_halvings", 31), ("delta0", 0.0),
+                                         ("delta0", float("nan"))])
 def test_rejects_bad_extension_settings(P, field, value):
     p = qpgen.workload("small", 3)
     _expect_invalid(P, *_args(p), match="settings", **{field: value})
@@ -165,6 +167,8 @@ def test_extension_defaults(P):
     assert s.fp32_promote == 1e-5
     assert s.delta_floor == 1.0
     assert s.fp32_stall == 50
+    assert s.external_halvings == 7
+    assert s.delta0 == 1.0
 
 
 def test_batch_and_network_argument_errors(P):

@@ -9,7 +9,7 @@ import pytest
 import qpgen
 from oracle import mlp_oracle as M
 from oracle import pdnqp_oracle as O
-from tests.test_gpu_parity import _gpu_kwargs
+from tests.test_gpu_parity import _gpu_kwargs, assert_meets_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -100,6 +100,7 @@ def test_controller_falls_back_to_adaptive_rule(P):
     _, _, info = s.solve(1e-4, 1e-4)
     assert info["controller_fallback"] == 1
     assert info["status"] == O.SOLVED
+    assert_meets_tolerance(info, 1e-4, 1e-4)
     assert C.sgm10([0.0, 0.0]) == pytest.approx(0.0)
 
 
@@ -122,6 +123,8 @@ def test_controller_gain_on_held_out_seeds(P):
         b.set_controller(theta)
         _, _, ib = b.solve(1e-4, 1e-4)
         assert ia["status"] == ib["status"] == O.SOLVED
+        assert_meets_tolerance(ia, 1e-4, 1e-4)
+        assert_meets_tolerance(ib, 1e-4, 1e-4)
         plain.append(ia["inner_accepted"])
         learned.append(ib["inner_accepted"])
     gm = lambda v: float(np.exp(np.mean(np.log(v))))

@@ -14,7 +14,7 @@ import pytest
 
 import qpgen
 from oracle import pdnqp_oracle as O
-from tests.test_gpu_parity import EDGE, _gpu_kwargs
+from tests.test_gpu_parity import EDGE, _gpu_kwargs, assert_meets_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +57,7 @@ def test_fp32_small_solve(P, seed):
     assert info["status"] == O.SOLVED
     assert info["r_p_scaled"] <= 1e-4 + 1e-4 * info["s_p_scaled"]
     assert info["r_d_scaled"] <= 1e-4 + 1e-4 * info["s_d_scaled"]
+    assert_meets_tolerance(info, 1e-4, 1e-4)
     # the reported final check is the FP64 KKT test of the returned point
     rp, rd, sp_, sd = O.external_kkt(prob, x, lam)
     assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
@@ -103,12 +104,14 @@ def test_fp32_promotes_below_its_attainable_tolerance(P):
     s = P.Solver.from_problem(prob, **kw)
     _, _, info = s.solve(1e-4, 1e-4)
     assert info["status"] == O.SOLVED and info["promoted_outer"] == 0
+    assert_meets_tolerance(info, 1e-4, 1e-4)
     s = P.Solver.from_problem(prob, **kw)
     x, lam, info = s.solve(1e-6, 1e-6)
     assert info["status"] == O.SOLVED
     assert info["promoted_outer"] >= 1
     assert info["r_p_scaled"] <= 1e-6 + 1e-6 * info["s_p_scaled"]
     assert info["r_d_scaled"] <= 1e-6 + 1e-6 * info["s_d_scaled"]
+    assert_meets_tolerance(info, 1e-6, 1e-6)
     rp, rd, _, _ = O.external_kkt(prob, x, lam)
     assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
     # the FP64 inner iteration before promotion is the plain FP32 one: a run

@@ -361,7 +361,7 @@ def test_mutation_penalty_inactive_rows_raised(monkeypatch):
 
 
 def test_mutation_centre_condition_inverted(monkeypatch):
-    def bad(x_new, z, r_p, s_p, eps_ak, eps_rk, st):
+    def bad(x_new, z, r_p, s_p, eps_ak, eps_rk, st, floor=None):
         if r_p > eps_ak + eps_rk * s_p:
             return x_new.copy(), eps_ak * st.rho_z, eps_rk * st.rho_z, True
         return z, eps_ak, eps_rk, False
@@ -370,7 +370,7 @@ def test_mutation_centre_condition_inverted(monkeypatch):
 
 
 def test_mutation_centre_tolerances_not_shrunk(monkeypatch):
-    def bad(x_new, z, r_p, s_p, eps_ak, eps_rk, st):
+    def bad(x_new, z, r_p, s_p, eps_ak, eps_rk, st, floor=None):
         if r_p <= eps_ak + eps_rk * s_p:
             return x_new.copy(), eps_ak, eps_rk, True
         return z, eps_ak, eps_rk, False
@@ -423,3 +423,43 @@ def test_mutation_two_sided_row_upper_side_dropped(monkeypatch):
         return orig(p2)
     monkeypatch.setattr(O, "normalise", bad)
     assert not _general_case_matches(("two", "two", "eq"), 1, time_limit=3.0)
+
+
+# ---------------------------------------------------------------------------
+# tolerance calibration of the experimental protocol (Section 4): a point is
+# accepted only when the KKT test on the caller's unscaled problem passes
+# ---------------------------------------------------------------------------
+
+def test_calibration_continues_until_unscaled_test_passes():
+    """Small seed 2 (Q-aware scaling): the scaled test passes first at a
+    point whose unscaled dual residual fails the external test; the internal
+    tolerances are halved once and the returned point passes both."""
+    p = qpgen.workload("small", 2)
+    tr = O.Trace()
+    res = O.solve(p, O.Settings(outer_scaling=2, max_outer=5000), trace=tr)
+    assert res.status == O.SOLVED and res.halvings == 1
+    assert O.passes_external(res, 1e-4, 1e-4)
+    k0, ea0, er0, rp0, rd0, sp0, sd0 = tr.external[0]
+    assert (ea0, er0) == (1e-4, 1e-4)
+    assert rd0 > 1e-4 + 1e-4 * sd0                      # the first candidate fails it
+    assert tr.external[-1][1:3] == (5e-5, 5e-5)
+    # stopping on the scaled test alone returns that first candidate
+    plain = O.solve(p, O.Settings(outer_scaling=2, max_outer=5000, external_halvings=0))
+    assert plain.status == O.SOLVED and plain.outer_iters == k0
+    assert not O.passes_external(plain, 1e-4, 1e-4)
+
+
+def test_calibration_limit_reports_inaccurate(monkeypatch):
+    """When the external test never passes, the run ends after the allowed
+    halvings (1/128 of the requested tolerances) with its own status."""
+    orig = O.external_kkt
+    calls = []
+
+    def failing(prob, x, lam):
+        rp, rd, sp_, sd = orig(prob, x, lam)
+        calls.append(1)
+        return rp, 1e9, sp_, sd
+    monkeypatch.setattr(O, "external_kkt", failing)
+    res = O.solve(qpgen.tiny_qp(3, 1, 1, 2), O.Settings(max_outer=20000))
+    assert res.status == O.INACCURATE
+    assert res.halvings == 7 and len(calls) == 8 + 1   # 8 candidates, then the final report
