@@ -71,8 +71,10 @@ def _cpu_model():
 
 def cpu_baseline(prob, n_inner):
     """FP64 CPU oracle on a bounded sample of the same instance: one outer
-    step whose inner solve is capped at ``n_inner`` accepted iterations
-    (checks after every 64).  The rate counts only the time spent inside the
+    step whose inner solve runs exactly ``n_inner`` accepted iterations
+    (checks after every 64; the initial inner tolerance is set to 1e-12 so
+    that the stopping test does not end the sample early -- the cost of an
+    iteration does not depend on it).  The rate counts only the time spent inside the
     oracle's inner solver (its set-up -- scaling, Lanczos, inner-QP
     formation -- is excluded).  The oracle runs on one core: every BLAS/
     OpenMP thread pool is limited to one thread for the whole leg (scipy's
@@ -92,7 +94,7 @@ def cpu_baseline(prob, n_inner):
     O.inner_solve = timed
     try:
         with threadpool_limits(limits=1):
-            st = O.Settings(max_outer=1, max_inner=n_inner)
+            st = O.Settings(max_outer=1, max_inner=n_inner, delta0=1e-12)
             t0 = time.perf_counter()
             r = O.solve(prob, st)
             total = time.perf_counter() - t0
@@ -106,10 +108,40 @@ def cpu_baseline(prob, n_inner):
     return {"value": round(rate, 3), "unit": "inner iters/s", "cores": 1, "kind": "oracle",
             "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(), "host_cpus_available": avail,
             "sample": (f"one outer step of the same n={prob['n']:,} instance with the inner "
-                       f"solve capped at {r.counters.accepted} accepted iterations "
+                       f"solve run for {r.counters.accepted} accepted iterations "
                        f"({r.counters.accepted // 64} stopping/restart checks); "
                        f"{spent[0]:.1f} s inside the inner solver ({total:.1f} s with the "
                        f"oracle's set-up); numpy/scipy FP64 on one thread")}
+
+
+def gather_bound(P, prob, dom, precision):
+    """Random-gather ceiling of the sparse products (pdnqp_probe_gather):
+    gathers per second for vectors of 1-64 MB in the element size of the
+    run, and what the dominant kernel's gathers cost at the rate measured
+    for its own gathered vector (x, n elements).  The per-trial product
+    kernels gather x[col] (Q without its diagonal, and A) or y[row] (A');
+    their speed is set by this rate, not by the matrix stream's bytes."""
+    import numpy as np
+    eb = 8 if precision == "fp64" else 4
+    table = []
+    for mb in (1, 2, 4, 8, 16, 64):
+        rate, _ = P.probe_gather((mb << 20) // eb, eb, 8_000_000, 10, 1)
+        table.append({"vector_MB": mb, "gathers_per_s": round(rate / 1e9, 2)})
+    Q = prob["Q"]
+    diag = int(np.count_nonzero(Q.diagonal()))
+    per_launch = {"qa_spmv": (Q.nnz - diag) + prob["A"].nnz, "at_spmv": prob["A"].nnz}
+    out = {"unit": "G gathers/s", "elem_bytes": eb, "probe": table}
+    g = per_launch.get(dom["name"])
+    if g is not None:
+        vec = prob["n"] if dom["name"] == "qa_spmv" else prob["m"]
+        rate, _ = P.probe_gather(vec, eb, g, 10, 2)
+        out.update({"kernel": dom["name"], "gathers_per_launch": g,
+                    "gathered_vector_MB": round(vec * eb / 2 ** 20, 2),
+                    "probe_rate_at_that_size": round(rate / 1e9, 2),
+                    "gather_time_us": round(g / rate * 1e6, 2),
+                    "kernel_avg_us": dom["avg_us"],
+                    "gather_frac": round((g / rate * 1e6) / dom["avg_us"], 4)})
+    return out
 
 
 def batch_leg(P, qpgen, args):
@@ -261,6 +293,7 @@ def main():
     del a, b
     roofline["copy_GBps"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(dom["GBps"] / copy_gbs, 4)
+    roofline["gather_bound"] = gather_bound(P, prob, dom, args.precision)
 
     ttt = None
     if not args.no_time_to_tol:

@@ -392,6 +392,20 @@ typedef struct pdnqp_kernel_stat {
 int pdnqp_kernel_stats(const pdnqp_solver *s, pdnqp_kernel_stat *out, int32_t cap,
                        int32_t *count);
 
+/* Measurement of the bound of the sparse products (Section 3.4: every inner
+ * iteration is a few sparse products whose columns, on the random
+ * instance families, are gathered at random positions).  On the current
+ * device: a vector of vec_len elements of elem_bytes (4 or 8) bytes and
+ * `gathers` seeded uniform positions in it; a kernel with the access
+ * pattern of the library's CSR-stream products (unit-stride, non-temporal
+ * index loads, then all of a thread's gathers at once) reads x[idx[k]] for
+ * every k, once to warm the caches, then `reps` times under HIP events.
+ * Writes the gathers per second and the average launch time (microseconds).
+ * Allocates and frees its own device buffers.  PDNQP_E_INVALID for a
+ * non-positive size or count or elem_bytes other than 4 and 8. */
+int pdnqp_probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
+                       uint64_t seed, double *gathers_per_s, double *launch_us);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpdnqp.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["pdnqp_kernels.hip", "pdnqp_iter.hip", "pdnqp_batch.hip", "pdnqp_solver.hip",
-           "pdnqp_mlp.hip", "pdnqp_api.cpp", "pdnqp_batch_host.cpp"]
+           "pdnqp_mlp.hip", "pdnqp_probe.hip", "pdnqp_api.cpp", "pdnqp_batch_host.cpp"]
 ARCH = os.environ.get("PDNQP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -379,6 +379,15 @@ int pdnqp_mlp_gradient(const float *theta, const float *x, const float *y, int32
   return r ? fail(r, err) : PDNQP_OK;
 }
 
+int pdnqp_probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
+                       uint64_t seed, double *gathers_per_s, double *launch_us) {
+  g_err.clear();
+  std::string err;
+  const int r = pdnqp::probe_gather(vec_len, elem_bytes, gathers, reps, seed, gathers_per_s,
+                                    launch_us, err);
+  return r ? fail(r, err) : PDNQP_OK;
+}
+
 int pdnqp_mlp_train(float *theta, const float *x, const float *y, int32_t count, int32_t epochs,
                     int32_t batch, float lr, uint64_t seed, float *loss_curve) {
   g_err.clear();

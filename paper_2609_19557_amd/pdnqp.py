@@ -148,8 +148,9 @@ EXPORTED = ["pdnqp_default_settings", "pdnqp_settings_size", "pdnqp_info_size", 
             "pdnqp_solve", "pdnqp_solve_batch", "pdnqp_destroy", "pdnqp_last_error",
             "pdnqp_dims", "pdnqp_get_trace", "pdnqp_kernel_stats", "pdnqp_batch_last_report",
             "pdnqp_batch_set_config", "pdnqp_batch_autotune", "pdnqp_mlp_forward",
-            "pdnqp_mlp_gradient", "pdnqp_mlp_train", "pdnqp_set_controller",
-            "pdnqp_get_outer_log"]
+            "pdnqp_mlp_gradient", "pdnqp_mlp_train",
+            "pdnqp_set_controller",
+            "pdnqp_get_outer_log", "pdnqp_probe_gather"]
 
 MLP_PARAMS, N_FEATURES, OUTER_RECORD = 5443, 16, 8
 
@@ -162,6 +163,21 @@ class PdnqpError(RuntimeError):
         self.code = code
 
 
+def _one_hip_runtime():
+    """Makes PyTorch's HIP runtime the process's only one, before the
+    library is loaded.  PyTorch's ROCm build ships its own runtime and asks
+    for it under the unversioned name ``libamdhip64.so``; the library asks
+    for ``libamdhip64.so.7``.  Loaded first, the library would map the
+    system runtime and a later ``import torch`` a second one, and device
+    pointers and streams would then cross runtimes.  With torch imported
+    first, the library's request is met by the runtime already mapped (same
+    soname).  Without PyTorch the library uses the system runtime."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def load(path=None):
     """Loads the library (once).  Raises if it is missing or mismatched."""
     global _lib
@@ -170,6 +186,7 @@ def load(path=None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise ImportError(f"{p} not found: build it first (python -m paper_2609_19557_amd.build)")
+    _one_hip_runtime()
     lib = ctypes.CDLL(p)
     i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     P = ctypes.POINTER
@@ -203,6 +220,9 @@ def load(path=None):
     lib.pdnqp_mlp_forward.restype = ctypes.c_int
     lib.pdnqp_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, P(dbl)]
     lib.pdnqp_mlp_gradient.restype = ctypes.c_int
+    lib.pdnqp_probe_gather.argtypes = [i32, i32, ctypes.c_int64, i32, ctypes.c_uint64,
+                                       P(dbl), P(dbl)]
+    lib.pdnqp_probe_gather.restype = ctypes.c_int
     lib.pdnqp_mlp_train.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
     lib.pdnqp_mlp_train.restype = ctypes.c_int
     lib.pdnqp_set_controller.argtypes = [vp, vp]
@@ -470,6 +490,18 @@ def mlp_gradient(theta, X, Y):
     if code != OK:
         raise _err(lib, code)
     return g, loss.value
+
+
+def probe_gather(vec_len, elem_bytes=8, gathers=8_000_000, reps=20, seed=1):
+    """Random-gather rate of the current device (pdnqp_probe_gather):
+    returns (gathers per second, average launch microseconds)."""
+    lib = load()
+    rate, us = ctypes.c_double(), ctypes.c_double()
+    code = lib.pdnqp_probe_gather(int(vec_len), int(elem_bytes), int(gathers), int(reps),
+                                  int(seed), ctypes.byref(rate), ctypes.byref(us))
+    if code != OK:
+        raise _err(lib, code)
+    return rate.value, us.value
 
 
 def mlp_train(theta, X, Y, epochs=200, batch=256, lr=1e-3, seed=0):

@@ -194,3 +194,20 @@ def test_batch_and_network_argument_errors(P):
                                ctypes.c_float(1e-3), 0, None) == -1
     assert lib.pdnqp_set_controller(None, th.ctypes.data) == -1
     assert lib.pdnqp_get_outer_log(None, None, None, None) == -1
+
+
+def test_one_hip_runtime_with_torch():
+    """Loading the library and then importing PyTorch maps one HIP runtime
+    (a second one would split device pointers and streams between
+    runtimes).  Runs in a fresh interpreter: the load order is what is
+    tested."""
+    import subprocess
+    import sys
+    code = ("import paper_2609_19557_amd as P; P.load(); import torch, re; "
+            "maps = open('/proc/self/maps').read(); "
+            "libs = sorted({m for m in re.findall(r'/\\S*libamdhip64\\S*', maps)}); "
+            "print(len(libs), libs)")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("1 "), out.stdout
