@@ -322,6 +322,25 @@ int pdnqp_mlp_forward(const float *theta, const float *x, int32_t count, float *
 int pdnqp_mlp_gradient(const float *theta, const float *x, const float *y, int32_t count,
                        float *grad, double *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * gradient and loss of pdnqp_mlp_gradient on caller-owned DEVICE buffers --
+ * theta (PDNQP_MLP_PARAMS floats), x (count x 16), y (count x 3), grad
+ * (PDNQP_MLP_PARAMS floats, written), loss (one double, written; may be
+ * NULL) -- enqueued on hip_stream (a hipStream_t; NULL: the default stream)
+ * of the current device, without synchronising; the results equal those of
+ * pdnqp_mlp_gradient bit for bit.  Calls no device allocation: the
+ * per-workgroup partial gradients live in a static device array of the
+ * library sized for PDNQP_MLP_NOALLOC_MAX samples (5.6 MB, held on each
+ * device the function runs on until the process ends; the first call on a
+ * device looks up its address).  PDNQP_E_INVALID for count outside
+ * [1, PDNQP_MLP_NOALLOC_MAX] or a NULL buffer; PDNQP_E_DEVICE if a launch
+ * fails.  Every call on one device shares that array: calls that overlap on
+ * one device (concurrent streams or threads) race. */
+enum { PDNQP_MLP_NOALLOC_MAX = 16384 };
+int pdnqp_mlp_gradient_noalloc(const float *theta, const float *x, const float *y, int32_t count,
+                               float *grad, double *loss, void *hip_stream);
+
 /* Adam (step lr, moments 0.9 / 0.999) on that loss over `epochs` passes of
  * shuffled minibatches of `batch` samples (seeded); theta is updated in
  * place; loss_curve (optional, `epochs` entries) gets the full-batch loss

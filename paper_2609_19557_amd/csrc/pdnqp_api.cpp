@@ -379,6 +379,16 @@ int pdnqp_mlp_gradient(const float *theta, const float *x, const float *y, int32
   return r ? fail(r, err) : PDNQP_OK;
 }
 
+int pdnqp_mlp_gradient_noalloc(const float *theta, const float *x, const float *y, int32_t count,
+                               float *grad, double *loss, void *hip_stream) {
+  g_err.clear();
+  if (!theta || !x || !y || !grad) return fail(PDNQP_E_INVALID, "invalid network arguments");
+  std::string err;
+  const int r = pdnqp::mlp_gradient_noalloc(theta, x, y, count, grad, loss,
+                                            (hipStream_t)hip_stream, err);
+  return r ? fail(r, err) : PDNQP_OK;
+}
+
 int pdnqp_probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
                        uint64_t seed, double *gathers_per_s, double *launch_us) {
   g_err.clear();

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -120,6 +121,16 @@ __global__ __launch_bounds__(kH) void k_mlp_grad(const float *__restrict__ th,
   if (j == 0) lossp[blockIdx.x] = lsum;
 }
 
+// Loss of the batch from the workgroups' parts, added in workgroup order in
+// FP64 (one thread: the same order and arithmetic as the host sum).
+__global__ void k_mlp_loss(const float *__restrict__ lossp, int nblk, int count,
+                           double *__restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += (double)lossp[b];
+  *loss = s / ((double)count * kOut);
+}
+
 // Adds the workgroups' partial gradients in workgroup order.
 __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ partial, int nblk,
                                                     float *__restrict__ grad) {
@@ -190,9 +201,75 @@ int grad_on_device(const float *th, const float *X, const float *Y, int count, f
   return hipc(hipGetLastError(), "mlp kernels", err);
 }
 
+// Scratch of the allocation-free gradient: the per-workgroup partial
+// gradients (kParams floats each) and loss parts of at most
+// kNoAllocMaxBlocks workgroups, i.e. kNoAllocMaxSamples samples (5.6 MB).
+// Each GPU the library runs on holds its own copy until the process ends.
+constexpr int kNoAllocMaxSamples = PDNQP_MLP_NOALLOC_MAX;
+constexpr int kNoAllocMaxBlocks = kNoAllocMaxSamples / kSamplesPerBlock;
+static_assert(kNoAllocMaxSamples % kSamplesPerBlock == 0, "whole workgroups");
+constexpr size_t kScratchFloats = (size_t)kNoAllocMaxBlocks * kParams + kNoAllocMaxBlocks;
+
+}  // namespace
+
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+
+// Device address of `scratch` per device, looked up once per device with the
+// device current (in host code the array's name is only a stand-in).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_current_device(float **out, std::string &err) {
+  int dev = 0;
+  int r = hipc(hipGetDevice(&dev), "hipGetDevice", err);
+  if (r) return r;
+  if (dev < 0 || dev >= kMaxDevices) {
+    err = "device index out of range";
+    return PDNQP_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if ((r = hipc(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress", err)))
+      return r;
+    if (!p) {
+      err = "hipGetSymbolAddress returned no address";
+      return PDNQP_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = (float *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PDNQP_OK;
+}
+
 }  // namespace
 
 int mlp_param_count() { return kParams; }
+
+// The gradient of mlp_gradient on caller-owned device buffers, with the
+// per-workgroup partials in the static scratch array: no device allocation,
+// no synchronisation (the work is enqueued on `st`).
+int mlp_gradient_noalloc(const float *theta, const float *X, const float *Y, int count,
+                         float *grad, double *loss, hipStream_t st, std::string &err) {
+  if (count < 1 || count > kNoAllocMaxSamples) {
+    err = "count must be in [1, " + std::to_string(kNoAllocMaxSamples) + "]";
+    return PDNQP_E_INVALID;
+  }
+  float *sp = nullptr;
+  int r = scratch_on_current_device(&sp, err);
+  if (r) return r;
+  const int nb = nblocks(count);
+  float *partial = sp;
+  float *lossp = sp + (size_t)kNoAllocMaxBlocks * kParams;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(kH), 0, st, theta, X, Y, count, partial, lossp);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + 255) / 256), dim3(256), 0, st, partial, nb,
+                     grad);
+  if (loss) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(64), 0, st, lossp, nb, count, loss);
+  return hipc(hipGetLastError(), "mlp kernels", err);
+}
 
 // Device-side forward of one feature vector with parameters already on the
 // device (the solver's controller).

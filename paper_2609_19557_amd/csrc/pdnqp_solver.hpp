@@ -196,6 +196,8 @@ void mlp_forward_device(hipStream_t st, const float *theta, const float *x, floa
 int mlp_forward(const float *theta, const float *X, int count, float *Y, std::string &err);
 int mlp_gradient(const float *theta, const float *X, const float *Y, int count, float *grad,
                  double *loss, std::string &err);
+int mlp_gradient_noalloc(const float *theta, const float *X, const float *Y, int count,
+                         float *grad, double *loss, hipStream_t st, std::string &err);
 int probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
                  uint64_t seed, double *rate, double *launch_us, std::string &err);
 int mlp_train(float *theta, const float *X, const float *Y, int count, int epochs, int batch,

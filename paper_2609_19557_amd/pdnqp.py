@@ -148,7 +148,7 @@ EXPORTED = ["pdnqp_default_settings", "pdnqp_settings_size", "pdnqp_info_size", 
             "pdnqp_solve", "pdnqp_solve_batch", "pdnqp_destroy", "pdnqp_last_error",
             "pdnqp_dims", "pdnqp_get_trace", "pdnqp_kernel_stats", "pdnqp_batch_last_report",
             "pdnqp_batch_set_config", "pdnqp_batch_autotune", "pdnqp_mlp_forward",
-            "pdnqp_mlp_gradient", "pdnqp_mlp_train",
+            "pdnqp_mlp_gradient", "pdnqp_mlp_gradient_noalloc", "pdnqp_mlp_train",
             "pdnqp_set_controller",
             "pdnqp_get_outer_log", "pdnqp_probe_gather"]
 
@@ -223,6 +223,8 @@ def load(path=None):
     lib.pdnqp_probe_gather.argtypes = [i32, i32, ctypes.c_int64, i32, ctypes.c_uint64,
                                        P(dbl), P(dbl)]
     lib.pdnqp_probe_gather.restype = ctypes.c_int
+    lib.pdnqp_mlp_gradient_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.pdnqp_mlp_gradient_noalloc.restype = ctypes.c_int
     lib.pdnqp_mlp_train.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
     lib.pdnqp_mlp_train.restype = ctypes.c_int
     lib.pdnqp_set_controller.argtypes = [vp, vp]
@@ -502,6 +504,18 @@ def probe_gather(vec_len, elem_bytes=8, gathers=8_000_000, reps=20, seed=1):
     if code != OK:
         raise _err(lib, code)
     return rate.value, us.value
+
+
+def mlp_gradient_noalloc(theta, x, y, count, grad, loss=None, stream=None):
+    """The allocation-free gradient entry point: every argument is a device
+    address (int) of a caller-owned buffer -- theta, x (count x 16), y
+    (count x 3), grad (written) and loss (one double, written; None to skip)
+    -- and ``stream`` a hipStream_t address (None: the default stream).  The
+    work is enqueued, not synchronised."""
+    lib = load()
+    code = lib.pdnqp_mlp_gradient_noalloc(theta, x, y, int(count), grad, loss, stream)
+    if code != OK:
+        raise _err(lib, code)
 
 
 def mlp_train(theta, X, Y, epochs=200, batch=256, lr=1e-3, seed=0):
