@@ -125,16 +125,17 @@ def gather_bound(P, prob, dom, precision):
     eb = 8 if precision == "fp64" else 4
     table = []
     for mb in (1, 2, 4, 8, 16, 64):
-        rate, _ = P.probe_gather((mb << 20) // eb, eb, 8_000_000, 10, 1)
+        rate, _ = P.probe_gather((mb << 20) // eb, eb, 8_000_000, reps=10, seed=1)
         table.append({"vector_MB": mb, "gathers_per_s": round(rate / 1e9, 2)})
     Q = prob["Q"]
     diag = int(np.count_nonzero(Q.diagonal()))
-    per_launch = {"qa_spmv": (Q.nnz - diag) + prob["A"].nnz, "at_spmv": prob["A"].nnz}
+    per_launch = {"qa_spmv": (Q.nnz - diag) + prob["A"].nnz,
+                  "qa_panels": (Q.nnz - diag) + prob["A"].nnz, "at_spmv": prob["A"].nnz}
     out = {"unit": "G gathers/s", "elem_bytes": eb, "probe": table}
     g = per_launch.get(dom["name"])
     if g is not None:
-        vec = prob["n"] if dom["name"] == "qa_spmv" else prob["m"]
-        rate, _ = P.probe_gather(vec, eb, g, 10, 2)
+        vec = prob["m"] if dom["name"] == "at_spmv" else prob["n"]
+        rate, _ = P.probe_gather(vec, eb, g, reps=10, seed=2)
         out.update({"kernel": dom["name"], "gathers_per_launch": g,
                     "gathered_vector_MB": round(vec * eb / 2 ** 20, 2),
                     "probe_rate_at_that_size": round(rate / 1e9, 2),
@@ -214,6 +215,9 @@ def main():
                     help="fp64 (the paper's arithmetic, default); fp32: FP32 matrix values and "
                          "inner vectors with FP64 reductions, FP64 outer update and final check "
                          "(the FP32-bulk extension, also timed as the other-precision leg)")
+    ap.add_argument("--col-panels", type=int, default=0, choices=[0, 1, 2],
+                    help="settings.col_panels of the timed solves: 0 automatic (two column "
+                         "panels when x exceeds one XCD's L2), 1 never, 2 always")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched workload (512 uneven instances, one persistent launch)")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -240,14 +244,15 @@ def main():
 
     # warm-up (separate handle, same data)
     sw = P.Solver.from_problem(prob, use_torch=True, max_outer=max(1, args.warmup),
-                               precision=P.FP32 if args.precision == "fp32" else P.FP64)
+                               precision=P.FP32 if args.precision == "fp32" else P.FP64,
+                               col_panels=args.col_panels)
     sw.solve(1e-4, 1e-4)
     sw.close()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
     prec = P.FP32 if args.precision == "fp32" else P.FP64
     s = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32,
-                              precision=prec)
+                              precision=prec, col_panels=args.col_panels)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x, lam, info = s.solve(1e-4, 1e-4)
@@ -298,7 +303,8 @@ def main():
     ttt = None
     if not args.no_time_to_tol:
         st = P.Solver.from_problem(prob, use_torch=True, outer_scaling=P.SCALE_RUIZ_QA,
-                                   time_limit_s=args.tol_time_limit, precision=prec)
+                                   time_limit_s=args.tol_time_limit, precision=prec,
+                                   col_panels=args.col_panels)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, _, inf2 = st.solve(1e-4, 1e-4)
@@ -315,7 +321,7 @@ def main():
     if not args.no_other_precision:
         oprec = P.FP64 if args.precision == "fp32" else P.FP32
         so = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32,
-                                   precision=oprec)
+                                   precision=oprec, col_panels=args.col_panels)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         _, _, io = so.solve(1e-4, 1e-4)

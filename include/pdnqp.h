@@ -163,6 +163,13 @@ typedef struct pdnqp_settings {
   void *alloc_user;
   double delta0;           /* [paper] initial inner tolerances delta_{a,0} = delta_{r,0}, 1
                               (Section 3.1, outer-loop initialization) */
+  int32_t col_panels;      /* the first sparse product of a trial (Q and A times the trial x)
+                              split into two column panels, each gathered by the workgroups of
+                              half of the XCDs, with a second launch adding the two partial
+                              row sums (same arithmetic up to the order of the two halves'
+                              sums): 0 (default) when the gathered vector exceeds one XCD's L2
+                              (4 MiB), 1 never, 2 always */
+  int32_t reserved_cp;
 } pdnqp_settings;
 
 /* Per-solve report. */
@@ -419,11 +426,15 @@ int pdnqp_kernel_stats(const pdnqp_solver *s, pdnqp_kernel_stat *out, int32_t ca
  * pattern of the library's CSR-stream products (unit-stride, non-temporal
  * index loads, then all of a thread's gathers at once) reads x[idx[k]] for
  * every k, once to warm the caches, then `reps` times under HIP events.
- * Writes the gathers per second and the average launch time (microseconds).
- * Allocates and frees its own device buffers.  PDNQP_E_INVALID for a
- * non-positive size or count or elem_bytes other than 4 and 8. */
-int pdnqp_probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
-                       uint64_t seed, double *gathers_per_s, double *launch_us);
+ * panels (1, 2, 4 or 8): the positions of each 2048-gather tile come from
+ * one of `panels` equal slices of the vector, and the tiles of one slice
+ * run on the same XCDs (workgroups are dispatched round-robin over the 8
+ * XCDs), as in a column-panel split of a product.  Writes the gathers per
+ * second and the average launch time (microseconds).  Allocates and frees
+ * its own device buffers.  PDNQP_E_INVALID for a non-positive size or
+ * count, elem_bytes other than 4 and 8, or another panel count. */
+int pdnqp_probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t panels,
+                       int32_t reps, uint64_t seed, double *gathers_per_s, double *launch_us);
 
 #ifdef __cplusplus
 }

@@ -162,7 +162,7 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         (st.controller != 0 && st.controller != 1) || st.outer_log < 0 ||
         !(st.fp32_promote >= 0) || !(st.delta_floor >= 0) || !std::isfinite(st.delta_floor) ||
         st.fp32_stall < 0 || st.external_halvings < 0 || st.external_halvings > 30 ||
-        !(st.delta0 > 0) || !std::isfinite(st.delta0))
+        !(st.delta0 > 0) || !std::isfinite(st.delta0) || st.col_panels < 0 || st.col_panels > 2)
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);
@@ -389,12 +389,12 @@ int pdnqp_mlp_gradient_noalloc(const float *theta, const float *x, const float *
   return r ? fail(r, err) : PDNQP_OK;
 }
 
-int pdnqp_probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
-                       uint64_t seed, double *gathers_per_s, double *launch_us) {
+int pdnqp_probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t panels,
+                       int32_t reps, uint64_t seed, double *gathers_per_s, double *launch_us) {
   g_err.clear();
   std::string err;
-  const int r = pdnqp::probe_gather(vec_len, elem_bytes, gathers, reps, seed, gathers_per_s,
-                                    launch_us, err);
+  const int r = pdnqp::probe_gather(vec_len, elem_bytes, gathers, panels, reps, seed,
+                                    gathers_per_s, launch_us, err);
   return r ? fail(r, err) : PDNQP_OK;
 }
 

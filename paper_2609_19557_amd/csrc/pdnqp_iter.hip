@@ -98,6 +98,80 @@ __global__ __launch_bounds__(kBlock) void k_xtrial(Ctrl *__restrict__ c, InnerPa
 //    plus the previous accept's averaging of ybar, rbar, sbar and the
 //    row-block parts of the acceptance sums (FP64).
 // ===========================================================================
+// Row-local part of the trial for constraint row j, given (A x_tr)_j: the
+// s and r trials, (B w_tr)_j, the dual extrapolation, the previous accept's
+// averaging of ybar, rbar, sbar, and the row parts of the acceptance sums.
+template <typename T>
+struct RowTrial {
+  int cur, nxt, pend, me;
+  T ap, alpha, beta, sct, scy;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+
+  __device__ __forceinline__ RowTrial(const Ctrl *__restrict__ c, const InnerParams &p) {
+    cur = c->cur;
+    nxt = cur ^ 1;
+    pend = c->pending;
+    me = p.me;
+    ap = (T)c->alpha_pend;
+    const double Nd = (double)c->N;
+    alpha = (T)(2.0 / (Nd + 2.0));
+    beta = (T)(Nd / (Nd + 1.0));
+    sct = (T)(c->step_scale / c->omega);
+    scy = (T)(c->step_scale * c->omega);
+  }
+
+  __device__ __forceinline__ void operator()(const IterVecs<T> &v, int j, T ax) {
+    const T y = v.Y[cur][j];
+    const T bw = v.BW[cur][j];
+    const T r = v.R[cur][j];
+    const T sg = v.sigma[j];
+    const T lm = v.lam[j];
+    const T bj = v.b[j];
+    T rb_ = v.rbar[j];
+    if (pend) {
+      v.ybar[j] = (T(1) - ap) * v.ybar[j] + ap * y;
+      rb_ = (T(1) - ap) * rb_ + ap * r;
+      v.rbar[j] = rb_;
+    }
+    const T gr = (T(1) - alpha) * (sg * rb_) + alpha * (sg * r) + lm + y;
+    const T tbr = v.taub_r[j];
+    const T rt = r - (sct * tbr) * gr;
+    T bwt, hj;
+    double ds = 0.0, ds2t = 0.0;
+    if (j < me) {
+      bwt = ax - rt;
+      hj = bj;
+    } else {
+      const int k = j - me;
+      const T sv = v.S[cur][k];
+      if (pend) v.sbar[k] = (T(1) - ap) * v.sbar[k] + ap * sv;
+      const T tbs = v.taub_s[k];
+      const T st = maxv<T>(sv - (sct * tbs) * y, bj);
+      v.S[nxt][k] = st;
+      bwt = ax - st - rt;
+      hj = T(0);
+      ds = (double)st - (double)sv;
+      ds2t = ds * ds / (double)tbs;
+    }
+    const T eb = v.etab[j];
+    const T yt = y + (scy * eb) * (hj - bwt - beta * (bwt - bw));
+    v.R[nxt][j] = rt;
+    v.BW[nxt][j] = bwt;
+    v.Y[nxt][j] = yt;
+    const double dr = (double)rt - (double)r;
+    const double dy = (double)yt - (double)y;
+    s1 += dr * dr / (double)tbr + ds2t;
+    s2 += dy * dy / (double)eb;
+    s3 += fabs(dr * ((double)sg * dr));
+    s4 += fabs(dr * dy) + fabs(ds * dy);
+  }
+
+  __device__ __forceinline__ void reduce(const IterVecs<T> &v, int slot) {
+    double vals[4] = {s1, s2, s3, s4};
+    block_reduce<4>(vals, 0u, v.partial + PS_ROW * kMaxParts, slot);
+  }
+};
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_qa_stream(Ctrl *__restrict__ c, InnerParams p,
                                                       IterVecs<T> v, CsrT<T> Q, CsrT<T> A, int gq,
@@ -115,64 +189,68 @@ __global__ __launch_bounds__(kBlock) void k_qa_stream(Ctrl *__restrict__ c, Inne
                      [&](int row, T s) { qxt[row] = s + qd[row] * xt[row]; });
   } else {
     const int b = blockIdx.x - gq;
-    const int pend = c->pending;
-    const T ap = (T)c->alpha_pend;
-    const double Nd = (double)c->N;
-    const T alpha = (T)(2.0 / (Nd + 2.0));
-    const T beta = (T)(Nd / (Nd + 1.0));
-    const T sct = (T)(c->step_scale / c->omega);
-    const T scy = (T)(c->step_scale * c->omega);
-    const int me = p.me;
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-    for (int rb = b; rb < A.nrb; rb += ga) {
-      stream_rows<T>(A, xt, A.rb[rb], A.rb[rb + 1], sprod, [&](int j, T ax) {
-        const T y = v.Y[cur][j];
-        const T bw = v.BW[cur][j];
-        const T r = v.R[cur][j];
-        const T sg = v.sigma[j];
-        const T lm = v.lam[j];
-        const T bj = v.b[j];
-        T rb_ = v.rbar[j];
-        if (pend) {
-          v.ybar[j] = (T(1) - ap) * v.ybar[j] + ap * y;
-          rb_ = (T(1) - ap) * rb_ + ap * r;
-          v.rbar[j] = rb_;
-        }
-        const T gr = (T(1) - alpha) * (sg * rb_) + alpha * (sg * r) + lm + y;
-        const T tbr = v.taub_r[j];
-        const T rt = r - (sct * tbr) * gr;
-        T bwt, hj;
-        double ds = 0.0, ds2t = 0.0;
-        if (j < me) {
-          bwt = ax - rt;
-          hj = bj;
-        } else {
-          const int k = j - me;
-          const T sv = v.S[cur][k];
-          if (pend) v.sbar[k] = (T(1) - ap) * v.sbar[k] + ap * sv;
-          const T tbs = v.taub_s[k];
-          const T st = maxv<T>(sv - (sct * tbs) * y, bj);
-          v.S[nxt][k] = st;
-          bwt = ax - st - rt;
-          hj = T(0);
-          ds = (double)st - (double)sv;
-          ds2t = ds * ds / (double)tbs;
-        }
-        const T eb = v.etab[j];
-        const T yt = y + (scy * eb) * (hj - bwt - beta * (bwt - bw));
-        v.R[nxt][j] = rt;
-        v.BW[nxt][j] = bwt;
-        v.Y[nxt][j] = yt;
-        const double dr = (double)rt - (double)r;
-        const double dy = (double)yt - (double)y;
-        s1 += dr * dr / (double)tbr + ds2t;
-        s2 += dy * dy / (double)eb;
-        s3 += fabs(dr * ((double)sg * dr));
-        s4 += fabs(dr * dy) + fabs(ds * dy);
-      });
+    RowTrial<T> rt(c, p);
+    for (int rb = b; rb < A.nrb; rb += ga)
+      stream_rows<T>(A, xt, A.rb[rb], A.rb[rb + 1], sprod, [&](int j, T ax) { rt(v, j, ax); });
+    rt.reduce(v, b);
+  }
+}
+
+// ===========================================================================
+// Column-panel form of the same trial part (two launches).  The columns of
+// Q_off and A are split at n/2 into two panels; each panel is a CSR of its
+// own over all rows, with its own stream row blocks.  k_qa_panels: workgroup
+// i works on panel i & 1 only -- workgroups are dispatched round-robin over
+// the 8 XCDs, so the workgroups of an XCD gather from one half of x_tr,
+// which stays in that XCD's L2 -- and writes each row's partial sum of its
+// panel.  k_qa_rows then adds the two partials of every row in panel order
+// and runs the same row epilogues as k_qa_stream.
+// ===========================================================================
+template <typename T>
+struct QAPanels {
+  CsrT<T> q0, q1, a0, a1;   // Q_off and A restricted to the two column panels
+  T *pq0, *pq1, *pa0, *pa1; // per-row partial sums of each panel
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_qa_panels(Ctrl *__restrict__ c, IterVecs<T> v,
+                                                      QAPanels<T> P) {
+  if (c->state != ST_RUNNING) return;
+  __shared__ T sprod[kTile];
+  const T *__restrict__ xt = v.X[c->cur ^ 1];
+  const bool h = (blockIdx.x & 1) != 0;
+  const CsrT<T> Q = h ? P.q1 : P.q0;
+  const CsrT<T> A = h ? P.a1 : P.a0;
+  T *__restrict__ pq = h ? P.pq1 : P.pq0;
+  T *__restrict__ pa = h ? P.pa1 : P.pa0;
+  const int items = Q.nrb + A.nrb;
+  const int step = (int)(gridDim.x >> 1);
+  for (int it = (int)(blockIdx.x >> 1); it < items; it += step) {
+    if (it < Q.nrb) {
+      stream_rows<T>(Q, xt, Q.rb[it], Q.rb[it + 1], sprod, [&](int row, T s) { pq[row] = s; });
+    } else {
+      const int b = it - Q.nrb;
+      stream_rows<T>(A, xt, A.rb[b], A.rb[b + 1], sprod, [&](int row, T s) { pa[row] = s; });
     }
-    double vals[4] = {s1, s2, s3, s4};
-    block_reduce<4>(vals, 0u, v.partial + PS_ROW * kMaxParts, b);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_qa_rows(Ctrl *__restrict__ c, InnerParams p,
+                                                    IterVecs<T> v, QAPanels<T> P, int gq, int ga) {
+  if (c->state != ST_RUNNING) return;
+  const int nxt = c->cur ^ 1;
+  if ((int)blockIdx.x < gq) {
+    const T *__restrict__ xt = v.X[nxt];
+    T *__restrict__ qxt = v.QX[nxt];
+    const T *__restrict__ qd = v.qdiag;
+    for_elems(p.n, blockIdx.x, gq,
+              [&](int i) { qxt[i] = (P.pq0[i] + P.pq1[i]) + qd[i] * xt[i]; });
+  } else {
+    const int b = blockIdx.x - gq;
+    RowTrial<T> rt(c, p);
+    for_elems(p.m, b, ga, [&](int j) { rt(v, j, P.pa0[j] + P.pa1[j]); });
+    rt.reduce(v, b);
   }
 }
 
@@ -774,6 +852,37 @@ void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> 
   launch_ev(k_qa_stream<T>, dim3(nz(gq + ga)), dim3(kBlock), st, ev, c, p, v, Q, A, gq, ga);
 }
 
+// Grid of the two-panel launch: both panels' items, interleaved (even
+// workgroups panel 0, odd panel 1), at most kMaxParts workgroups.
+static int qa_panels_grid(int items0, int items1) {
+  const int half = std::min(std::max(items0, items1), kMaxParts / 2);
+  return 2 * nz(half);
+}
+
+// Workgroups of the row-combine launch: Q rows, then A rows (the A part
+// writes one acceptance partial per workgroup).
+static int qa_rows_blocks(int rows) {
+  return nz((int)std::min<int64_t>(((int64_t)rows + kBlock - 1) / kBlock, 1024));
+}
+
+template <typename T>
+void launch_qa_panels(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                      const QAPanelSet<T> &P, LaunchEvents ev) {
+  QAPanels<T> k{P.q[0], P.q[1], P.a[0], P.a[1], P.pq[0], P.pq[1], P.pa[0], P.pa[1]};
+  const int grid = qa_panels_grid(P.q[0].nrb + P.a[0].nrb, P.q[1].nrb + P.a[1].nrb);
+  launch_ev(k_qa_panels<T>, dim3(grid), dim3(kBlock), st, ev, c, v, k);
+  (void)p;
+}
+
+template <typename T>
+void launch_qa_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                    const QAPanelSet<T> &P, LaunchEvents ev) {
+  QAPanels<T> k{P.q[0], P.q[1], P.a[0], P.a[1], P.pq[0], P.pq[1], P.pa[0], P.pa[1]};
+  const int gq = qa_rows_blocks(p.n);
+  const int ga = p.m ? qa_rows_blocks(p.m) : 0;
+  launch_ev(k_qa_rows<T>, dim3(gq + ga), dim3(kBlock), st, ev, c, p, v, k, gq, ga);
+}
+
 template <typename T>
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                const CsrT<T> &AT, LaunchEvents ev) {
@@ -782,9 +891,9 @@ void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> 
 }
 
 void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
-                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev) {
+                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev, bool panels) {
   const int gx = xtrial_blocks(p.n);
-  const int ga = std::min(a_nrb, kMaxParts);
+  const int ga = panels ? (p.m ? qa_rows_blocks(p.m) : 0) : std::min(a_nrb, kMaxParts);
   const int gt = nz(std::min(at_nrb, kMaxParts));
   launch_ev(k_decide, dim3(1), dim3(kDecideThreads), st, ev, c, p, partial, trace_tr, gx, ga, gt);
 }
@@ -858,6 +967,10 @@ void launch_cast(hipStream_t st, D *dst, const S *src, int64_t n) {
                              const CsrT<T> &, const CsrT<T> &, LaunchEvents);                    \
   template void launch_at<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,      \
                              const CsrT<T> &, LaunchEvents);                                     \
+  template void launch_qa_panels<T>(hipStream_t, Ctrl *, const InnerParams &,                    \
+                                    const IterVecs<T> &, const QAPanelSet<T> &, LaunchEvents);   \
+  template void launch_qa_rows<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &, \
+                                  const QAPanelSet<T> &, LaunchEvents);                          \
   template void launch_trace<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &);  \
   template void launch_flush<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,   \
                                 const Part &, const Part &);                                     \

@@ -189,9 +189,25 @@ void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> 
 template <typename T>
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                const CsrT<T> &AT, LaunchEvents ev = {});
-// acceptance test of the trial (one workgroup), after launch_at
+// Two-panel form of launch_qa: Q_off and A split by columns at n/2, each
+// half a CSR over all rows with its own stream row blocks, and the per-row
+// partial sums of each half (device buffers of n and m values).
+template <typename T>
+struct QAPanelSet {
+  CsrT<T> q[2], a[2];
+  T *pq[2], *pa[2];
+};
+template <typename T>
+void launch_qa_panels(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                      const QAPanelSet<T> &P, LaunchEvents ev = {});
+template <typename T>
+void launch_qa_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
+                    const QAPanelSet<T> &P, LaunchEvents ev = {});
+// acceptance test of the trial (one workgroup), after launch_at; `panels`:
+// the row part of the sums came from launch_qa_rows
 void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
-                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev = {});
+                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev = {},
+                   bool panels = false);
 template <typename T>
 void launch_trace(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v);
 template <typename T>

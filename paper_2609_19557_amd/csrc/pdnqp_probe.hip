@@ -9,6 +9,13 @@
 // CSR-stream kernels: each thread loads kStreamE indices with unit stride
 // (non-temporal, like the matrix stream), then issues its kStreamE
 // gathers at once and adds them; one sum per workgroup is written.
+//
+// With P > 1 column panels, the positions of tile b are drawn from panel
+// b mod P only (the vector's P equal slices), and workgroup i processes the
+// tiles b = i (mod grid) with grid a multiple of 8: since workgroups are
+// dispatched round-robin over the 8 XCDs, the workgroups of one XCD then
+// read one slice only, which is what a column-panel split of a sparse
+// product would give.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,17 +75,23 @@ int hipc(hipError_t e, const char *what, std::string &err) {
 
 }  // namespace
 
-int probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
-                 uint64_t seed, double *rate, double *launch_us, std::string &err) {
-  if (vec_len < 1 || (elem_bytes != 4 && elem_bytes != 8) || gathers < 1 || reps < 1) {
+int probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t panels,
+                 int32_t reps, uint64_t seed, double *rate, double *launch_us, std::string &err) {
+  if (vec_len < 1 || (elem_bytes != 4 && elem_bytes != 8) || gathers < 1 || reps < 1 ||
+      panels < 1 || panels > 8 || (8 % panels) != 0 || panels > vec_len) {
     err = "invalid probe arguments";
     return PDNQP_E_INVALID;
   }
   std::vector<int32_t> hidx((size_t)gathers);
   std::mt19937_64 rng(seed);
-  std::uniform_int_distribution<int32_t> pick(0, vec_len - 1);
-  for (auto &v : hidx) v = pick(rng);
-  const int grid = (int)std::min<int64_t>((gathers + kTile - 1) / kTile, 65536);
+  const int32_t width = vec_len / panels;  // the last panel also takes the remainder
+  for (int64_t k = 0; k < gathers; ++k) {
+    const int p = (int)((k / kTile) % panels);
+    const int32_t lo = p * width, hi = (p == panels - 1) ? vec_len - 1 : lo + width - 1;
+    hidx[(size_t)k] = std::uniform_int_distribution<int32_t>(lo, hi)(rng);
+  }
+  int64_t tiles = (gathers + kTile - 1) / kTile;
+  const int grid = (int)std::min<int64_t>((tiles + 7) / 8 * 8, 65536);
   Buf x, idx, out;
   int r;
   if ((r = hipc(hipMalloc(&x.p, (size_t)vec_len * elem_bytes), "hipMalloc", err)) ||

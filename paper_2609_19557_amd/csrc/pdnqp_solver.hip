@@ -73,7 +73,30 @@ double ninf(const std::vector<double> &v) {
   return m;
 }
 
-enum TimerId { TM_XTRIAL = 0, TM_QA = 1, TM_AT = 2, TM_DECIDE = 3, TM_COUNT = 4 };
+enum TimerId { TM_XTRIAL = 0, TM_QA = 1, TM_AT = 2, TM_DECIDE = 3, TM_QA_ROWS = 4, TM_COUNT = 5 };
+
+// The columns of a CSR split at `mid` into two CSRs over all rows: panel 0
+// holds the entries with column < mid, panel 1 the others, each in the
+// original order within a row; perm[h][k] is the original position of entry
+// k of panel h.
+struct ColumnSplit {
+  std::vector<int32_t> p[2], i[2], perm[2];
+};
+
+ColumnSplit split_columns(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                          int32_t rows, int32_t mid) {
+  ColumnSplit s;
+  for (int h = 0; h < 2; ++h) s.p[h].assign((size_t)rows + 1, 0);
+  for (int32_t r = 0; r < rows; ++r) {
+    for (int32_t k = rp[r]; k < rp[r + 1]; ++k) {
+      const int h = ci[k] < mid ? 0 : 1;
+      s.i[h].push_back(ci[k]);
+      s.perm[h].push_back(k);
+    }
+    for (int h = 0; h < 2; ++h) s.p[h][(size_t)r + 1] = (int32_t)s.i[h].size();
+  }
+  return s;
+}
 
 }  // namespace
 
@@ -276,6 +299,62 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   Qr_ = Csr{Qp_, Qi_, Qraw_, n, GQ, qrb, nq, 0};
   Ar_ = Csr{Ap_, Ai_, Araw_, m, GA, arb, na, 0};
   ATr_ = Csr{ATp_, ATi_, ATraw_, n, GT, atrb, nt, 0};
+  // two column panels for the first trial product when the gathered vector
+  // x_tr is larger than one XCD's L2 (4 MiB): FP64 from n > 512Ki, FP32 from
+  // n > 1Mi (settings.col_panels: 0 that rule, 1 never, 2 always)
+  constexpr double kL2Bytes = 4.0 * 1024 * 1024;
+  panels64_ = st_.col_panels == 2 || (st_.col_panels == 0 && 8.0 * n > kL2Bytes);
+  panels32_ = fp32_ && (st_.col_panels == 2 || (st_.col_panels == 0 && 4.0 * n > kL2Bytes));
+  if (panels64_ || panels32_) {
+    const int32_t mid = n / 2;
+    const ColumnSplit sq = split_columns(qp_.Qop, qp_.Qoi, n, mid);
+    const ColumnSplit sa = split_columns(qp_.Ap, qp_.Ai, m, mid);
+    for (int h = 0; h < 2; ++h) {
+      pnnz_q_[h] = (int64_t)sq.i[h].size();
+      pnnz_a_[h] = (int64_t)sa.i[h].size();
+      const size_t nq1 = (size_t)std::max<int64_t>(pnnz_q_[h], 1);
+      const size_t na1 = (size_t)std::max<int64_t>(pnnz_a_[h], 1);
+      int32_t *qp = I(n + 1), *qi = I(nq1), *ap = I(m + 1), *ai = I(na1);
+      pperm_q_[h] = I(nq1);
+      pperm_a_[h] = I(na1);
+      double *qv = D(nq1), *av = D(na1);
+      qap64_.pq[h] = D(n);
+      qap64_.pa[h] = D(std::max(m, 1));
+      if (!ok) {
+        err = "device allocation failed";
+        return PDNQP_E_NOMEM;
+      }
+      chain(H2D(qp, sq.p[h].data(), (size_t)(n + 1) * 4));
+      chain(H2D(qi, sq.i[h].data(), (size_t)pnnz_q_[h] * 4));
+      chain(H2D(pperm_q_[h], sq.perm[h].data(), (size_t)pnnz_q_[h] * 4));
+      chain(H2D(ap, sa.p[h].data(), (size_t)(m + 1) * 4));
+      chain(H2D(ai, sa.i[h].data(), (size_t)pnnz_a_[h] * 4));
+      chain(H2D(pperm_a_[h], sa.perm[h].data(), (size_t)pnnz_a_[h] * 4));
+      int32_t *qrbh = nullptr, *arbh = nullptr, nqh = 0, nah = 0;
+      if (!blocks_of(sq.p[h], n, qrbh, nqh) || !blocks_of(sa.p[h], m, arbh, nah)) {
+        err = "row-block upload failed";
+        return PDNQP_E_DEVICE;
+      }
+      qap64_.q[h] = Csr{qp, qi, qv, n, 1, qrbh, nqh, 0};
+      qap64_.a[h] = Csr{ap, ai, av, m, 1, arbh, nah, 0};
+      if (panels32_) {
+        float *qv32 = (float *)dalloc((size_t)std::max<int64_t>(pnnz_q_[h], 1) * 4);
+        float *av32 = (float *)dalloc((size_t)std::max<int64_t>(pnnz_a_[h], 1) * 4);
+        float *pq32 = (float *)dalloc((size_t)n * 4);
+        float *pa32 = (float *)dalloc((size_t)std::max(m, 1) * 4);
+        if (!qv32 || !av32 || !pq32 || !pa32) {
+          err = "device allocation failed";
+          return PDNQP_E_NOMEM;
+        }
+        qap32_.q[h] = CsrT<float>{qp, qi, qv32, n, 1, qrbh, nqh, 0};
+        qap32_.a[h] = CsrT<float>{ap, ai, av32, m, 1, arbh, nah, 0};
+        qap32_.pq[h] = pq32;
+        qap32_.pa[h] = pa32;
+      }
+    }
+    chain(hipStreamSynchronize(stream_));
+    if ((r = check(e, "panel upload", err))) return r;
+  }
   px_ = make_part(n, 1, 512);
   ps_ = make_part(mi, 1, 256);
   pr_ = make_part(m, 1, 256);
@@ -289,6 +368,7 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   timers_[TM_QA].name = "qa_spmv";
   timers_[TM_AT].name = "at_spmv";
   timers_[TM_DECIDE].name = "decide";
+  timers_[TM_QA_ROWS].name = "qa_rows";
   const double me = qp_.me;
   const double vb = fp32_ ? 4.0 : 8.0;  // bytes per value of the bulk type
   timers_[TM_XTRIAL].bytes = 12.0 * vb * n;
@@ -298,6 +378,16 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
                          4.0 * (m + 1) + vb * n + 15.0 * vb * me + 20.0 * vb * mi;
   timers_[TM_AT].bytes = (4.0 + vb) * nza + 4.0 * (n + 1) + vb * m + vb * n + 5.0 * vb * n;
   timers_[TM_DECIDE].bytes = 0.0;
+  timers_[TM_QA_ROWS].bytes = 0.0;
+  if (fp32_ ? panels32_ : panels64_) {
+    // the two-panel form: values and indices once, both panels' row
+    // pointers, x_tr once, one partial per row and panel written; then the
+    // partials read back, and the Q and A row epilogues of the one-launch form
+    timers_[TM_QA].name = "qa_panels";
+    timers_[TM_QA].bytes = (4.0 + vb) * (nzo + nza) + 8.0 * (n + 1) + 8.0 * (m + 1) + vb * n +
+                           2.0 * vb * (n + m);
+    timers_[TM_QA_ROWS].bytes = 2.0 * vb * (n + m) + 3.0 * vb * n + 15.0 * vb * me + 20.0 * vb * mi;
+  }
   return PDNQP_OK;
 }
 
@@ -417,6 +507,12 @@ int Solver::setup(const double *x0c, const double *lam0_int, double &c_obj, doub
   launch_elem(stream_, EL_DIAG, qdiag_, v_.Dx, qdiag_raw_, c_obj, n);
   launch_scale_csr(stream_, Ap_, Ai_, Av_, m, v_.Dc, v_.Dx, 1.0, pa_);
   launch_gather(stream_, ATv_, Av_, atperm_, (int64_t)qp_.Ai.size());
+  if (panels64_ || panels32_) {
+    for (int h = 0; h < 2; ++h) {
+      launch_gather(stream_, const_cast<double *>(qap64_.q[h].v), Qov_, pperm_q_[h], pnnz_q_[h]);
+      launch_gather(stream_, const_cast<double *>(qap64_.a[h].v), Av_, pperm_a_[h], pnnz_a_[h]);
+    }
+  }
   launch_elem(stream_, EL_MULS, c_, v_.Dx, craw_, c_obj, n);
   launch_elem(stream_, EL_MUL, b_, v_.Dc, braw_, 0.0, m);
   launch_elem(stream_, EL_DIV, lo_, xlraw_, v_.Dx, 0.0, n);
@@ -464,6 +560,14 @@ int Solver::setup(const double *x0c, const double *lam0_int, double &c_obj, doub
     launch_cast<float, double>(stream_, Qo32v_, Qov_, (int64_t)qp_.Qoi.size());
     launch_cast<float, double>(stream_, A32v_, Av_, (int64_t)qp_.Ai.size());
     launch_cast<float, double>(stream_, AT32v_, ATv_, (int64_t)qp_.Ai.size());
+    if (panels32_) {
+      for (int h = 0; h < 2; ++h) {
+        launch_cast<float, double>(stream_, const_cast<float *>(qap32_.q[h].v), qap64_.q[h].v,
+                                   pnnz_q_[h]);
+        launch_cast<float, double>(stream_, const_cast<float *>(qap32_.a[h].v), qap64_.a[h].v,
+                                   pnnz_a_[h]);
+      }
+    }
     launch_cast<float, double>(stream_, const_cast<float *>(iv32_.qdiag), qdiag_, n);
     launch_cast<float, double>(stream_, const_cast<float *>(iv32_.lo), lo_, n);
     launch_cast<float, double>(stream_, const_cast<float *>(iv32_.hi), hi_, n);
@@ -551,19 +655,44 @@ void Solver::cast_state_to64(int cur) {
   launch_cast<double, float>(stream_, v_.Y[cur], iv32_.Y[cur], qp_.m);
 }
 
+template <>
+bool Solver::use_panels<double>() const {
+  return panels64_;
+}
+template <>
+bool Solver::use_panels<float>() const {
+  return panels32_;
+}
+template <>
+const QAPanelSet<double> &Solver::panel_set<double>() const {
+  return qap64_;
+}
+template <>
+const QAPanelSet<float> &Solver::panel_set<float>() const {
+  return qap32_;
+}
+
 // One chunk of trial slots followed by the check kernels.  Slots after a
 // due check (or after the inner limit) find the state not running and exit
 // at once, so the full chunk can always be enqueued.
 template <typename T>
 void Solver::enqueue_chunk(int slots, bool sampled, const IterVecs<T> &iv, const CsrT<T> &Qo,
                            const CsrT<T> &A, const CsrT<T> &AT) {
+  const bool panels = use_panels<T>();
   for (int s = 0; s < slots; ++s) {
     sample_now_ = sampled && st_.profile > 0 && (slot_count_++ % st_.profile) == 0;
     timed_launch(TM_XTRIAL, [&](LaunchEvents e) { launch_xtrial<T>(stream_, ctrl_, ip_, iv, e); });
-    timed_launch(TM_QA, [&](LaunchEvents e) { launch_qa<T>(stream_, ctrl_, ip_, iv, Qo, A, e); });
+    if (panels) {
+      const QAPanelSet<T> &ps = panel_set<T>();
+      timed_launch(TM_QA, [&](LaunchEvents e) { launch_qa_panels<T>(stream_, ctrl_, ip_, iv, ps, e); });
+      timed_launch(TM_QA_ROWS,
+                   [&](LaunchEvents e) { launch_qa_rows<T>(stream_, ctrl_, ip_, iv, ps, e); });
+    } else {
+      timed_launch(TM_QA, [&](LaunchEvents e) { launch_qa<T>(stream_, ctrl_, ip_, iv, Qo, A, e); });
+    }
     timed_launch(TM_AT, [&](LaunchEvents e) { launch_at<T>(stream_, ctrl_, ip_, iv, AT, e); });
     timed_launch(TM_DECIDE, [&](LaunchEvents e) {
-      launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, A.nrb, AT.nrb, e);
+      launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, A.nrb, AT.nrb, e, panels);
     });
     if (trace_iters_cap_ > 0) launch_trace<T>(stream_, ctrl_, ip_, iv);
   }

@@ -134,6 +134,18 @@ class Solver {
   IterVecs<float> iv32_{};
   CsrT<float> Qo32_{}, A32_{}, AT32_{};
   float *Qo32v_ = nullptr, *A32v_ = nullptr, *AT32v_ = nullptr;
+  // two-column-panel form of the first trial product (settings.col_panels):
+  // per precision whether it is used, the panels (values gathered from the
+  // scaled Q_off and A through the permutations) and the partial sums
+  bool panels64_ = false, panels32_ = false;
+  QAPanelSet<double> qap64_{};
+  QAPanelSet<float> qap32_{};
+  int32_t *pperm_q_[2] = {nullptr, nullptr}, *pperm_a_[2] = {nullptr, nullptr};
+  int64_t pnnz_q_[2] = {0, 0}, pnnz_a_[2] = {0, 0};
+  template <typename T>
+  bool use_panels() const;
+  template <typename T>
+  const QAPanelSet<T> &panel_set() const;
   Part px_{}, ps_{}, pr_{}, pq_{}, pa_{}, pt_{};
   InnerParams ip_{};
   double gamma_ = 0.0;
@@ -198,8 +210,8 @@ int mlp_gradient(const float *theta, const float *X, const float *Y, int count, 
                  double *loss, std::string &err);
 int mlp_gradient_noalloc(const float *theta, const float *X, const float *Y, int count,
                          float *grad, double *loss, hipStream_t st, std::string &err);
-int probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t reps,
-                 uint64_t seed, double *rate, double *launch_us, std::string &err);
+int probe_gather(int32_t vec_len, int32_t elem_bytes, int64_t gathers, int32_t panels,
+                 int32_t reps, uint64_t seed, double *rate, double *launch_us, std::string &err);
 int mlp_train(float *theta, const float *X, const float *Y, int count, int epochs, int batch,
               float lr, uint64_t seed, float *loss_curve, std::string &err);
 

@@ -78,6 +78,8 @@ class Settings(ctypes.Structure):
         ("dev_free", _FREE_FN),
         ("alloc_user", ctypes.c_void_p),
         ("delta0", ctypes.c_double),
+        ("col_panels", ctypes.c_int32),
+        ("reserved_cp", ctypes.c_int32),
     ]
 
 
@@ -220,7 +222,7 @@ def load(path=None):
     lib.pdnqp_mlp_forward.restype = ctypes.c_int
     lib.pdnqp_mlp_gradient.argtypes = [vp, vp, vp, i32, vp, P(dbl)]
     lib.pdnqp_mlp_gradient.restype = ctypes.c_int
-    lib.pdnqp_probe_gather.argtypes = [i32, i32, ctypes.c_int64, i32, ctypes.c_uint64,
+    lib.pdnqp_probe_gather.argtypes = [i32, i32, ctypes.c_int64, i32, i32, ctypes.c_uint64,
                                        P(dbl), P(dbl)]
     lib.pdnqp_probe_gather.restype = ctypes.c_int
     lib.pdnqp_mlp_gradient_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp]
@@ -494,13 +496,13 @@ def mlp_gradient(theta, X, Y):
     return g, loss.value
 
 
-def probe_gather(vec_len, elem_bytes=8, gathers=8_000_000, reps=20, seed=1):
+def probe_gather(vec_len, elem_bytes=8, gathers=8_000_000, reps=20, seed=1, panels=1):
     """Random-gather rate of the current device (pdnqp_probe_gather):
     returns (gathers per second, average launch microseconds)."""
     lib = load()
     rate, us = ctypes.c_double(), ctypes.c_double()
-    code = lib.pdnqp_probe_gather(int(vec_len), int(elem_bytes), int(gathers), int(reps),
-                                  int(seed), ctypes.byref(rate), ctypes.byref(us))
+    code = lib.pdnqp_probe_gather(int(vec_len), int(elem_bytes), int(gathers), int(panels),
+                                  int(reps), int(seed), ctypes.byref(rate), ctypes.byref(us))
     if code != OK:
         raise _err(lib, code)
     return rate.value, us.value

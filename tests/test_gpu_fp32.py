@@ -30,14 +30,15 @@ def _relmax(a, b):
     return np.abs(a - b).max() / max(1.0, np.abs(b).max())
 
 
+@pytest.mark.parametrize("panels", [1, 2])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_fp32_tracks_fp64_oracle(P, seed):
+def test_fp32_tracks_fp64_oracle(P, seed, panels):
     prob = qpgen.workload("small", seed)
     st = O.Settings(max_outer=3, outer_scaling=2)
     tr = O.Trace(max_iters=40)
     O.solve(prob, st, trace=tr)
     s = P.Solver.from_problem(prob, precision=P.FP32, trace_iters=40, trace_trials=80,
-                              **_gpu_kwargs(st))
+                              col_panels=panels, **_gpu_kwargs(st))
     s.solve(st.eps_abs, st.eps_rel)
     t = s.trace()
     n = min(len(tr.w), t["w"].shape[0])

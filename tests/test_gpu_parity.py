@@ -50,10 +50,11 @@ def _gpu_kwargs(st: O.Settings):
     return kw
 
 
-def run_pair(P, prob, st, iters=1000, trials=4000):
+def run_pair(P, prob, st, iters=1000, trials=4000, **lib_only):
     tr = O.Trace(max_iters=iters)
     res_o = O.solve(prob, st, trace=tr)
-    s = P.Solver.from_problem(prob, trace_iters=iters, trace_trials=trials, **_gpu_kwargs(st))
+    s = P.Solver.from_problem(prob, trace_iters=iters, trace_trials=trials, **_gpu_kwargs(st),
+                              **lib_only)
     x, lam, info = s.solve(st.eps_abs, st.eps_rel)
     t = s.trace()
     return res_o, tr, (x, lam, info), t, s
@@ -135,6 +136,20 @@ def test_small_first_1000_iterations(P, seed, mode):
     assert_iterate_parity(tr, t, n_expect=1000)
     assert_decision_parity(tr, t, window_of(tr))
     assert info["gamma"] == pytest.approx(res_o.gamma, rel=1e-10)
+
+
+@pytest.mark.parametrize("seed", [1, 3])
+def test_two_panel_form_first_1000_iterations(P, seed):
+    """The two-column-panel form of the first trial product (forced here; by
+    default it runs only when x exceeds one XCD's L2): same iterates and
+    decisions as the oracle."""
+    prob = qpgen.workload("small", seed)
+    st = _oracle_settings(max_outer=40, outer_scaling=2)
+    res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, col_panels=2)
+    assert_iterate_parity(tr, t, n_expect=1000)
+    assert_decision_parity(tr, t, window_of(tr))
+    names = {k["name"] for k in s.kernel_stats()}
+    assert "qa_panels" in names and "qa_rows" in names
 
 
 @pytest.mark.parametrize("seed", [1, 2])
@@ -237,11 +252,13 @@ def _edge_cases():
 EDGE = _edge_cases()
 
 
+@pytest.mark.parametrize("panels", [1, 2])
 @pytest.mark.parametrize("name", sorted(EDGE))
-def test_edge_cases_iterate_parity(P, name):
+def test_edge_cases_iterate_parity(P, name, panels):
     prob = EDGE[name]
     st = _oracle_settings(max_outer=12, outer_scaling=2)
-    res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, iters=400, trials=800)
+    res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, iters=400, trials=800,
+                                               col_panels=panels)
     assert_iterate_parity(tr, t)
     assert_decision_parity(tr, t, window_of(tr))
     assert info["status"] == res_o.status
