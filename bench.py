@@ -34,11 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the device code they were taken on: the hash covers the
 # kernel helpers and the kernels of the inner iteration, not the host-side
 # launch wrappers.
-PMC_TRAFFIC = {"source_sha256_prefix": "e5cd270ae9ce3ec3", "workload": "large",
-               "bytes": {"f32": {"xtrial": 48.1e6, "qa_spmv": 219.8e6, "at_spmv": 81.2e6,
+PMC_TRAFFIC = {"source_sha256_prefix": "9972908cbbf3e593", "workload": "large",
+               "bytes": {"f32": {"xtrial": 48.0e6, "qa_spmv": 220.1e6, "at_spmv": 80.9e6,
                                  "decide": 0.1e6},
-                         "f64": {"xtrial": 96.1e6, "qa_spmv": 750.4e6, "at_spmv": 194.0e6,
-                                 "decide": 0.1e6}}}
+                         "f64": {"xtrial": 95.9e6, "qa_panels": 253.1e6, "qa_rows": 118.0e6,
+                                 "at_spmv": 194.0e6, "decide": 0.1e6}}}
 
 
 def _kernel_source_sha():
@@ -135,9 +135,10 @@ def gather_bound(P, prob, dom, precision):
     g = per_launch.get(dom["name"])
     if g is not None:
         vec = prob["m"] if dom["name"] == "at_spmv" else prob["n"]
-        rate, _ = P.probe_gather(vec, eb, g, reps=10, seed=2)
+        panels = 2 if dom["name"] == "qa_panels" else 1
+        rate, _ = P.probe_gather(vec, eb, g, reps=10, seed=2, panels=panels)
         out.update({"kernel": dom["name"], "gathers_per_launch": g,
-                    "gathered_vector_MB": round(vec * eb / 2 ** 20, 2),
+                    "gathered_vector_MB": round(vec * eb / 2 ** 20, 2), "panels": panels,
                     "probe_rate_at_that_size": round(rate / 1e9, 2),
                     "gather_time_us": round(g / rate * 1e6, 2),
                     "kernel_avg_us": dom["avg_us"],
