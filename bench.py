@@ -216,6 +216,8 @@ def main():
                     help="fp64 (the paper's arithmetic, default); fp32: FP32 matrix values and "
                          "inner vectors with FP64 reductions, FP64 outer update and final check "
                          "(the FP32-bulk extension, also timed as the other-precision leg)")
+    ap.add_argument("--stream-grid", type=int, default=0,
+                    help="settings.stream_grid of the timed solves (0 automatic)")
     ap.add_argument("--col-panels", type=int, default=0, choices=[0, 1, 2],
                     help="settings.col_panels of the timed solves: 0 automatic (two column "
                          "panels when x exceeds one XCD's L2), 1 never, 2 always")
@@ -246,14 +248,16 @@ def main():
     # warm-up (separate handle, same data)
     sw = P.Solver.from_problem(prob, use_torch=True, max_outer=max(1, args.warmup),
                                precision=P.FP32 if args.precision == "fp32" else P.FP64,
-                               col_panels=args.col_panels)
+                               col_panels=args.col_panels,
+                               stream_grid=args.stream_grid)
     sw.solve(1e-4, 1e-4)
     sw.close()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
 
     prec = P.FP32 if args.precision == "fp32" else P.FP64
     s = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32,
-                              precision=prec, col_panels=args.col_panels)
+                              precision=prec, col_panels=args.col_panels,
+                              stream_grid=args.stream_grid)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x, lam, info = s.solve(1e-4, 1e-4)
@@ -305,7 +309,7 @@ def main():
     if not args.no_time_to_tol:
         st = P.Solver.from_problem(prob, use_torch=True, outer_scaling=P.SCALE_RUIZ_QA,
                                    time_limit_s=args.tol_time_limit, precision=prec,
-                                   col_panels=args.col_panels)
+                                   col_panels=args.col_panels, stream_grid=args.stream_grid)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, _, inf2 = st.solve(1e-4, 1e-4)
@@ -322,7 +326,8 @@ def main():
     if not args.no_other_precision:
         oprec = P.FP64 if args.precision == "fp32" else P.FP32
         so = P.Solver.from_problem(prob, use_torch=True, max_outer=args.steps, profile=32,
-                                   precision=oprec, col_panels=args.col_panels)
+                                   precision=oprec, col_panels=args.col_panels,
+                                   stream_grid=args.stream_grid)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         _, _, io = so.solve(1e-4, 1e-4)

@@ -169,7 +169,10 @@ typedef struct pdnqp_settings {
                               row sums (same arithmetic up to the order of the two halves'
                               sums): 0 (default) when the gathered vector exceeds one XCD's L2
                               (4 MiB), 1 never, 2 always */
-  int32_t reserved_cp;
+  int32_t stream_grid;     /* workgroups of the pipelined CSR-stream product launches of a
+                              trial (the column-panel product and the A' product; a launch
+                              tuning knob: it changes only the order in which per-workgroup
+                              acceptance sums are added): 0 (default) 2048, else 2..4096 */
 } pdnqp_settings;
 
 /* Per-solve report. */

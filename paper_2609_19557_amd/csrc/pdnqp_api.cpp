@@ -162,7 +162,8 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         (st.controller != 0 && st.controller != 1) || st.outer_log < 0 ||
         !(st.fp32_promote >= 0) || !(st.delta_floor >= 0) || !std::isfinite(st.delta_floor) ||
         st.fp32_stall < 0 || st.external_halvings < 0 || st.external_halvings > 30 ||
-        !(st.delta0 > 0) || !std::isfinite(st.delta0) || st.col_panels < 0 || st.col_panels > 2)
+        !(st.delta0 > 0) || !std::isfinite(st.delta0) || st.col_panels < 0 || st.col_panels > 2 ||
+        st.stream_grid < 0 || st.stream_grid == 1 || st.stream_grid > 4096)
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);

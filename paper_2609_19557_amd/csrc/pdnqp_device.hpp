@@ -210,6 +210,119 @@ __device__ __forceinline__ void stream_rows(const CsrT<T> &M, const T *__restric
   }
 }
 
+// One row block of a CSR-stream product as a pipeline stage: the matrix it
+// belongs to (tag tells the caller which), its rows [r0, r1), its nonzeros
+// [base, base + cnt) and, once loaded, this thread's E of them.
+template <typename T, int E>
+struct StreamTile {
+  const int32_t *p;
+  const int32_t *ci;
+  const T *cv;
+  int tag, r0, r1, base, cnt;
+  int col[E];
+  T val[E];
+};
+
+// Fills the bounds of row block b of M: the row range from M.rb[0..nrb] and
+// the nonzero range from the offsets stored after it, M.rb[nrb + 1 + b].
+template <typename T, int E>
+__device__ __forceinline__ void tile_bounds(const CsrT<T> &M, int b, int tag,
+                                            StreamTile<T, E> &t) {
+  t.p = M.p;
+  t.ci = M.i;
+  t.cv = M.v;
+  t.tag = tag;
+  t.r0 = M.rb[b];
+  t.r1 = M.rb[b + 1];
+  const int32_t *nz = M.rb + M.nrb + 1;
+  t.base = nz[b];
+  t.cnt = nz[b + 1] - t.base;
+}
+
+// Loads this thread's nonzeros of a tile with unit stride (nothing for a
+// block holding a single row longer than a tile).
+template <typename T, int E>
+__device__ __forceinline__ void tile_load(StreamTile<T, E> &t) {
+  const bool fits = t.cnt <= E * kBlock;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = e * kBlock + threadIdx.x;
+    t.col[e] = 0;
+    t.val[e] = T(0);
+    if (fits && k < t.cnt) {
+      t.col[e] = __builtin_nontemporal_load(&t.ci[t.base + k]);
+      t.val[e] = __builtin_nontemporal_load(&t.cv[t.base + k]);
+    }
+  }
+}
+
+// Software-pipelined CSR-stream products over the row blocks it0, it0 +
+// step, ... (< items) of one workgroup, for row blocks of at most E * kBlock
+// nonzeros (a longer block holds a single row).  sel(it, tile) fills a
+// tile's bounds.  While the gathers of block it are in flight the nonzeros
+// of the next block are loaded, and the bounds of the one after are read at
+// the end of each step, so a workgroup keeps the matrix stream and the
+// gathers of x busy at the same time instead of in turn.  Products are
+// staged in LDS (sprod: E * kBlock entries) and one thread per row adds its
+// products in order, as in stream_rows, so the sums are the same;
+// emit(tag, row, sum) runs on that thread.
+template <typename T, int E, typename Sel, typename Emit>
+__device__ __forceinline__ void stream_pipelined(int it0, int items, int step,
+                                                 const T *__restrict__ x, T *__restrict__ sprod,
+                                                 Sel &&sel, Emit &&emit) {
+  if (it0 >= items) return;
+  StreamTile<T, E> cur, nxt;
+  sel(it0, cur);
+  tile_load(cur);
+  int nit = it0 + step;
+  if (nit < items) sel(nit, nxt);
+  for (;;) {
+    const bool more = nit < items;
+    if (cur.cnt <= E * kBlock) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = e * kBlock + threadIdx.x;
+        if (k < cur.cnt) cur.val[e] = cur.val[e] * x[cur.col[e]];
+      }
+      if (more) tile_load(nxt);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int k = e * kBlock + threadIdx.x;
+        if (k < cur.cnt) sprod[k] = cur.val[e];
+      }
+      __syncthreads();
+      for (int row = cur.r0 + (int)threadIdx.x; row < cur.r1; row += kBlock) {
+        const int a = cur.p[row] - cur.base;
+        const int b = cur.p[row + 1] - cur.base;
+        T s = T(0);
+        for (int k = a; k < b; ++k) s += sprod[k];
+        emit(cur.tag, row, s);
+      }
+      __syncthreads();
+    } else {
+      if (more) tile_load(nxt);
+      __shared__ T red[kWaves];
+      T s = T(0);
+      for (int k = threadIdx.x; k < cur.cnt; k += kBlock)
+        s += cur.cv[cur.base + k] * x[cur.ci[cur.base + k]];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        T t = red[0];
+        for (int w = 1; w < kWaves; ++w) t += red[w];
+        emit(cur.tag, cur.r0, t);
+      }
+      __syncthreads();
+    }
+    if (!more) break;
+    cur = nxt;
+    nit += step;
+    if (nit < items) sel(nit, nxt);
+  }
+}
+
 }  // namespace dev
 }  // namespace pdnqp
 

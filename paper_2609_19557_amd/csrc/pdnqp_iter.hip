@@ -177,21 +177,24 @@ __global__ __launch_bounds__(kBlock) void k_qa_stream(Ctrl *__restrict__ c, Inne
                                                       IterVecs<T> v, CsrT<T> Q, CsrT<T> A, int gq,
                                                       int ga) {
   if (c->state != ST_RUNNING) return;
-  __shared__ T sprod[kTile];
+  __shared__ T sprod[kPipeTile];
   const int cur = c->cur;
   const int nxt = cur ^ 1;
   const T *__restrict__ xt = v.X[nxt];
   if ((int)blockIdx.x < gq) {
     T *__restrict__ qxt = v.QX[nxt];
     const T *__restrict__ qd = v.qdiag;
-    for (int rb = blockIdx.x; rb < Q.nrb; rb += gq)
-      stream_rows<T>(Q, xt, Q.rb[rb], Q.rb[rb + 1], sprod,
-                     [&](int row, T s) { qxt[row] = s + qd[row] * xt[row]; });
+    stream_pipelined<T, kPipeE>(
+        (int)blockIdx.x, Q.nrb, gq, xt, sprod,
+        [&](int b, StreamTile<T, kPipeE> &t) { tile_bounds(Q, b, 0, t); },
+        [&](int, int row, T s) { qxt[row] = s + qd[row] * xt[row]; });
   } else {
     const int b = blockIdx.x - gq;
     RowTrial<T> rt(c, p);
-    for (int rb = b; rb < A.nrb; rb += ga)
-      stream_rows<T>(A, xt, A.rb[rb], A.rb[rb + 1], sprod, [&](int j, T ax) { rt(v, j, ax); });
+    stream_pipelined<T, kPipeE>(
+        b, A.nrb, ga, xt, sprod,
+        [&](int rb, StreamTile<T, kPipeE> &t) { tile_bounds(A, rb, 0, t); },
+        [&](int, int j, T ax) { rt(v, j, ax); });
     rt.reduce(v, b);
   }
 }
@@ -216,7 +219,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_qa_panels(Ctrl *__restrict__ c, IterVecs<T> v,
                                                       QAPanels<T> P) {
   if (c->state != ST_RUNNING) return;
-  __shared__ T sprod[kTile];
+  __shared__ T sprod[kPipeTile];
   const T *__restrict__ xt = v.X[c->cur ^ 1];
   const bool h = (blockIdx.x & 1) != 0;
   const CsrT<T> Q = h ? P.q1 : P.q0;
@@ -225,14 +228,15 @@ __global__ __launch_bounds__(kBlock) void k_qa_panels(Ctrl *__restrict__ c, Iter
   T *__restrict__ pa = h ? P.pa1 : P.pa0;
   const int items = Q.nrb + A.nrb;
   const int step = (int)(gridDim.x >> 1);
-  for (int it = (int)(blockIdx.x >> 1); it < items; it += step) {
-    if (it < Q.nrb) {
-      stream_rows<T>(Q, xt, Q.rb[it], Q.rb[it + 1], sprod, [&](int row, T s) { pq[row] = s; });
-    } else {
-      const int b = it - Q.nrb;
-      stream_rows<T>(A, xt, A.rb[b], A.rb[b + 1], sprod, [&](int row, T s) { pa[row] = s; });
-    }
-  }
+  stream_pipelined<T, kPipeE>(
+      (int)(blockIdx.x >> 1), items, step, xt, sprod,
+      [&](int it, StreamTile<T, kPipeE> &t) {
+        if (it < Q.nrb)
+          tile_bounds(Q, it, 0, t);
+        else
+          tile_bounds(A, it - Q.nrb, 1, t);
+      },
+      [&](int tag, int row, T s) { (tag ? pa : pq)[row] = s; });
 }
 
 template <typename T>
@@ -260,22 +264,23 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_at_stream(Ctrl *__restrict__ c, InnerParams p,
                                                       IterVecs<T> v, CsrT<T> AT) {
   if (c->state != ST_RUNNING) return;
-  __shared__ T sprod[kTile];
+  __shared__ T sprod[kPipeTile];
   const int cur = c->cur;
   const int nxt = cur ^ 1;
   const double gi = p.gamma_inv;
   const T *__restrict__ yt = v.Y[nxt];
   double s5 = 0.0, s6 = 0.0;
-  for (int rb = blockIdx.x; rb < AT.nrb; rb += gridDim.x) {
-    stream_rows<T>(AT, yt, AT.rb[rb], AT.rb[rb + 1], sprod, [&](int i, T a) {
-      v.ATY[nxt][i] = a;
-      const double dx = (double)v.X[nxt][i] - (double)v.X[cur][i];
-      const double hdx = ((double)v.QX[nxt][i] - (double)v.QX[cur][i]) + gi * dx;
-      const double ady = (double)a - (double)v.ATY[cur][i];
-      s5 += fabs(dx * hdx);
-      s6 += fabs(dx * ady);
-    });
-  }
+  stream_pipelined<T, kPipeE>(
+      (int)blockIdx.x, AT.nrb, (int)gridDim.x, yt, sprod,
+      [&](int b, StreamTile<T, kPipeE> &t) { tile_bounds(AT, b, 0, t); },
+      [&](int, int i, T a) {
+        v.ATY[nxt][i] = a;
+        const double dx = (double)v.X[nxt][i] - (double)v.X[cur][i];
+        const double hdx = ((double)v.QX[nxt][i] - (double)v.QX[cur][i]) + gi * dx;
+        const double ady = (double)a - (double)v.ATY[cur][i];
+        s5 += fabs(dx * hdx);
+        s6 += fabs(dx * ady);
+      });
   double vals[2] = {s5, s6};
   block_reduce<2>(vals, 0u, v.partial + PS_AT * kMaxParts, blockIdx.x);
 }
@@ -818,6 +823,24 @@ __global__ __launch_bounds__(kBlock) void k_cast(D *__restrict__ dst, const S *_
 
 inline int nz(int b) { return b > 0 ? b : 1; }
 
+// Workgroups of the single-launch first product: the pipelined grid
+// (kPipeGrid or the caller's stream_grid) split between the row blocks of
+// Q_off (gq) and of A (ga, one acceptance partial each) in proportion to
+// their counts; no A workgroups without constraint rows.
+void qa_split(int qnrb, int anrb, int stream_grid, int &gq, int &ga) {
+  const int G = stream_grid > 0 ? stream_grid : kPipeGrid;
+  if (anrb <= 0) {
+    gq = nz(std::min(qnrb, G));
+    ga = 0;
+    return;
+  }
+  const int64_t tot = (int64_t)qnrb + anrb;
+  int q = (int)(((int64_t)G * qnrb + tot / 2) / tot);
+  q = std::max(1, std::min(q, G - 1));
+  gq = nz(std::min(qnrb, q));
+  ga = nz(std::min(anrb, G - q));
+}
+
 }  // namespace
 
 int xtrial_blocks(int n) {
@@ -847,16 +870,23 @@ void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs
 template <typename T>
 void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                const CsrT<T> &Q, const CsrT<T> &A, LaunchEvents ev) {
-  const int gq = std::min(Q.nrb, kMaxParts);
-  const int ga = std::min(A.nrb, kMaxParts);
-  launch_ev(k_qa_stream<T>, dim3(nz(gq + ga)), dim3(kBlock), st, ev, c, p, v, Q, A, gq, ga);
+  int gq, ga;
+  qa_split(Q.nrb, A.nrb, p.stream_grid, gq, ga);
+  launch_ev(k_qa_stream<T>, dim3(gq + ga), dim3(kBlock), st, ev, c, p, v, Q, A, gq, ga);
 }
 
 // Grid of the two-panel launch: both panels' items, interleaved (even
-// workgroups panel 0, odd panel 1), at most kMaxParts workgroups.
-static int qa_panels_grid(int items0, int items1) {
-  const int half = std::min(std::max(items0, items1), kMaxParts / 2);
+// workgroups panel 0, odd panel 1), at most kPipeGrid workgroups or the
+// caller's stream_grid.
+static int qa_panels_grid(int items0, int items1, int stream_grid) {
+  const int cap = std::max((stream_grid > 0 ? stream_grid : kPipeGrid) / 2, 1);
+  const int half = std::min(std::max(items0, items1), cap);
   return 2 * nz(half);
+}
+
+// Grid of the A' launch (one acceptance partial per workgroup).
+static int at_grid(int nrb, int stream_grid) {
+  return nz(std::min(nrb, stream_grid > 0 ? stream_grid : kPipeGrid));
 }
 
 // Workgroups of the row-combine launch: Q rows, then A rows (the A part
@@ -869,9 +899,9 @@ template <typename T>
 void launch_qa_panels(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                       const QAPanelSet<T> &P, LaunchEvents ev) {
   QAPanels<T> k{P.q[0], P.q[1], P.a[0], P.a[1], P.pq[0], P.pq[1], P.pa[0], P.pa[1]};
-  const int grid = qa_panels_grid(P.q[0].nrb + P.a[0].nrb, P.q[1].nrb + P.a[1].nrb);
+  const int grid =
+      qa_panels_grid(P.q[0].nrb + P.a[0].nrb, P.q[1].nrb + P.a[1].nrb, p.stream_grid);
   launch_ev(k_qa_panels<T>, dim3(grid), dim3(kBlock), st, ev, c, v, k);
-  (void)p;
 }
 
 template <typename T>
@@ -886,15 +916,20 @@ void launch_qa_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVec
 template <typename T>
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                const CsrT<T> &AT, LaunchEvents ev) {
-  const int g = std::min(AT.nrb, kMaxParts);
-  launch_ev(k_at_stream<T>, dim3(nz(g)), dim3(kBlock), st, ev, c, p, v, AT);
+  launch_ev(k_at_stream<T>, dim3(at_grid(AT.nrb, p.stream_grid)), dim3(kBlock), st, ev, c, p, v,
+            AT);
 }
 
 void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
-                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev, bool panels) {
+                   double *trace_tr, int q_nrb, int a_nrb, int at_nrb, LaunchEvents ev,
+                   bool panels) {
   const int gx = xtrial_blocks(p.n);
-  const int ga = panels ? (p.m ? qa_rows_blocks(p.m) : 0) : std::min(a_nrb, kMaxParts);
-  const int gt = nz(std::min(at_nrb, kMaxParts));
+  int gq_unused = 0, ga = 0;
+  if (panels)
+    ga = p.m ? qa_rows_blocks(p.m) : 0;
+  else
+    qa_split(q_nrb, a_nrb, p.stream_grid, gq_unused, ga);
+  const int gt = at_grid(at_nrb, p.stream_grid);
   launch_ev(k_decide, dim3(1), dim3(kDecideThreads), st, ev, c, p, partial, trace_tr, gx, ga, gt);
 }
 

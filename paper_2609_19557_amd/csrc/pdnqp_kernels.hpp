@@ -21,6 +21,13 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64s)
 constexpr int kMaxParts = 4096;    // upper bound of reduction partials per launch
 constexpr int kStreamE = 8;        // CSR-stream: nonzeros per thread per row block
 constexpr int kTile = kStreamE * kBlock;  // CSR-stream: nonzeros per row block (2048)
+// software-pipelined CSR-stream kernels (two row blocks in flight per
+// workgroup): nonzeros per thread and per row block, and the default grid
+// (measured at n = 1M: 4 nonzeros per thread, or grids of 1024-4096, are
+// no faster; 512 is slower)
+constexpr int kPipeE = 8;
+constexpr int kPipeTile = kPipeE * kBlock;
+constexpr int kPipeGrid = 2048;
 
 enum State : int32_t {
   ST_RUNNING = 0,
@@ -92,7 +99,8 @@ constexpr int kAASums = kAAMem * (kAAMem + 1) / 2 + kAAMem;  // 44
 struct InnerParams {
   int32_t n, m, me, mi;
   int32_t check_every, max_inner, max_rejects, mode_init;
-  int32_t trace_iters_cap, trace_trials_cap, dw, pad;
+  int32_t trace_iters_cap, trace_trials_cap, dw;
+  int32_t stream_grid;  // workgroups of the CSR-stream product launches (0: automatic)
   double gamma_inv;
   double delta_a, delta_r;
   double h_norm;       // ||h||_inf = ||b_E||_inf
@@ -107,7 +115,8 @@ struct CsrT {
   const T *v;
   int32_t rows;
   int32_t G;           // lanes per row (power of two, 2..32) of the row-group kernels
-  const int32_t *rb;   // CSR-stream row blocks: block b owns rows [rb[b], rb[b+1])
+  const int32_t *rb;   // CSR-stream row blocks: block b owns rows [rb[b], rb[b+1]) and
+                       // nonzeros [rb[nrb+1+b], rb[nrb+2+b])
   int32_t nrb;         // number of row blocks
   int32_t pad;
 };
@@ -203,10 +212,11 @@ void launch_qa_panels(hipStream_t st, Ctrl *c, const InnerParams &p, const IterV
 template <typename T>
 void launch_qa_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                     const QAPanelSet<T> &P, LaunchEvents ev = {});
-// acceptance test of the trial (one workgroup), after launch_at; `panels`:
-// the row part of the sums came from launch_qa_rows
+// acceptance test of the trial (one workgroup), after launch_at; the row
+// block counts of Q_off, A and A' give the partial counts of the launches
+// before it; `panels`: the row part of the sums came from launch_qa_rows
 void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
-                   double *trace_tr, int a_nrb, int at_nrb, LaunchEvents ev = {},
+                   double *trace_tr, int q_nrb, int a_nrb, int at_nrb, LaunchEvents ev = {},
                    bool panels = false);
 template <typename T>
 void launch_trace(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v);

@@ -271,19 +271,24 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
 
   const int GQ = pick_G(nzq, n), GA = pick_G(nza, m), GT = pick_G(nza, n);
   // CSR-stream row blocks of the three matrices
+  // (tile: nonzeros per block, kTile for the single-stage kernels, kPipeTile
+  // for the pipelined ones: A' and the column panels)
   auto blocks_of = [&](const std::vector<int32_t> &rp, int32_t rows, int32_t *&dev,
-                       int32_t &nrb) -> bool {
-    std::vector<int32_t> rb(rows + 2);
-    stream_row_blocks(rp.data(), rows, 4 * kBlock, &nrb, rb.data());
-    dev = (int32_t *)dalloc((size_t)(nrb + 1) * 4);
+                       int32_t &nrb, int32_t tile) -> bool {
+    // row boundaries of the nrb blocks, then the nonzero offset of each
+    std::vector<int32_t> rb(2 * (size_t)rows + 4);
+    stream_row_blocks(rp.data(), rows, 4 * kBlock, &nrb, rb.data(), tile);
+    for (int32_t b = 0; b <= nrb; ++b) rb[nrb + 1 + b] = rp[rb[b]];
+    dev = (int32_t *)dalloc((size_t)(nrb + 1) * 8);
     if (!dev) return false;
-    return hipMemcpyAsync(dev, rb.data(), (size_t)(nrb + 1) * 4, hipMemcpyHostToDevice,
+    return hipMemcpyAsync(dev, rb.data(), (size_t)(nrb + 1) * 8, hipMemcpyHostToDevice,
                           stream_) == hipSuccess;
   };
   int32_t *qrb = nullptr, *arb = nullptr, *atrb = nullptr, *qorb = nullptr;
   int32_t nq = 0, na = 0, nt = 0, nqo = 0;
-  if (!blocks_of(qp_.Qp, n, qrb, nq) || !blocks_of(qp_.Ap, m, arb, na) ||
-      !blocks_of(qp_.ATp, n, atrb, nt) || !blocks_of(qp_.Qop, n, qorb, nqo)) {
+  if (!blocks_of(qp_.Qp, n, qrb, nq, kTile) || !blocks_of(qp_.Ap, m, arb, na, kPipeTile) ||
+      !blocks_of(qp_.ATp, n, atrb, nt, kPipeTile) ||
+      !blocks_of(qp_.Qop, n, qorb, nqo, kPipeTile)) {
     err = "row-block upload failed";
     return PDNQP_E_DEVICE;
   }
@@ -331,7 +336,8 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
       chain(H2D(ai, sa.i[h].data(), (size_t)pnnz_a_[h] * 4));
       chain(H2D(pperm_a_[h], sa.perm[h].data(), (size_t)pnnz_a_[h] * 4));
       int32_t *qrbh = nullptr, *arbh = nullptr, nqh = 0, nah = 0;
-      if (!blocks_of(sq.p[h], n, qrbh, nqh) || !blocks_of(sa.p[h], m, arbh, nah)) {
+      if (!blocks_of(sq.p[h], n, qrbh, nqh, kPipeTile) ||
+          !blocks_of(sa.p[h], m, arbh, nah, kPipeTile)) {
         err = "row-block upload failed";
         return PDNQP_E_DEVICE;
       }
@@ -363,6 +369,7 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   pt_ = make_part(n, GT, 1024);
   ip_ = InnerParams{};
   ip_.n = n; ip_.m = m; ip_.me = qp_.me; ip_.mi = mi; ip_.dw = n + mi + m;
+  ip_.stream_grid = st_.stream_grid;
   timers_.resize(TM_COUNT);
   timers_[TM_XTRIAL].name = "xtrial";
   timers_[TM_QA].name = "qa_spmv";
@@ -692,7 +699,8 @@ void Solver::enqueue_chunk(int slots, bool sampled, const IterVecs<T> &iv, const
     }
     timed_launch(TM_AT, [&](LaunchEvents e) { launch_at<T>(stream_, ctrl_, ip_, iv, AT, e); });
     timed_launch(TM_DECIDE, [&](LaunchEvents e) {
-      launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, A.nrb, AT.nrb, e, panels);
+      launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, Qo.nrb, A.nrb, AT.nrb, e,
+                    panels);
     });
     if (trace_iters_cap_ > 0) launch_trace<T>(stream_, ctrl_, ip_, iv);
   }

@@ -79,7 +79,7 @@ class Settings(ctypes.Structure):
         ("alloc_user", ctypes.c_void_p),
         ("delta0", ctypes.c_double),
         ("col_panels", ctypes.c_int32),
-        ("reserved_cp", ctypes.c_int32),
+        ("stream_grid", ctypes.c_int32),
     ]
 
 

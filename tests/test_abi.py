@@ -154,7 +154,9 @@ def test_null_handle_calls_are_errors(P):
                                          ("delta_floor", -0.5), ("delta_floor", float("inf")),
                                          ("fp32_stall", -1), ("external_halvings", -1),
                                          ("external_halvings", 31), ("delta0", 0.0),
-                                         ("delta0", float("nan"))])
+                                         ("delta0", float("nan")), ("col_panels", 3),
+                                         ("stream_grid", -1), ("stream_grid", 1),
+                                         ("stream_grid", 4097)])
 def test_rejects_bad_extension_settings(P, field, value):
     p = qpgen.workload("small", 3)
     _expect_invalid(P, *_args(p), match="settings", **{field: value})

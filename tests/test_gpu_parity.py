@@ -138,14 +138,15 @@ def test_small_first_1000_iterations(P, seed, mode):
     assert info["gamma"] == pytest.approx(res_o.gamma, rel=1e-10)
 
 
-@pytest.mark.parametrize("seed", [1, 3])
-def test_two_panel_form_first_1000_iterations(P, seed):
+@pytest.mark.parametrize("seed,grid", [(1, 0), (3, 0), (1, 2), (3, 6)])
+def test_two_panel_form_first_1000_iterations(P, seed, grid):
     """The two-column-panel form of the first trial product (forced here; by
     default it runs only when x exceeds one XCD's L2): same iterates and
-    decisions as the oracle."""
+    decisions as the oracle.  Grids of 2 and 6 workgroups make every
+    workgroup of the pipelined product launches walk many row blocks."""
     prob = qpgen.workload("small", seed)
     st = _oracle_settings(max_outer=40, outer_scaling=2)
-    res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, col_panels=2)
+    res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, col_panels=2, stream_grid=grid)
     assert_iterate_parity(tr, t, n_expect=1000)
     assert_decision_parity(tr, t, window_of(tr))
     names = {k["name"] for k in s.kernel_stats()}
