@@ -172,7 +172,7 @@ typedef struct pdnqp_settings {
   int32_t stream_grid;     /* workgroups of the pipelined CSR-stream product launches of a
                               trial (the column-panel product and the A' product; a launch
                               tuning knob: it changes only the order in which per-workgroup
-                              acceptance sums are added): 0 (default) 2048, else 2..4096 */
+                              acceptance sums are added): 0 (default) 1024, else 2..4096 */
 } pdnqp_settings;
 
 /* Per-solve report. */

@@ -23,11 +23,12 @@ constexpr int kStreamE = 8;        // CSR-stream: nonzeros per thread per row bl
 constexpr int kTile = kStreamE * kBlock;  // CSR-stream: nonzeros per row block (2048)
 // software-pipelined CSR-stream kernels (two row blocks in flight per
 // workgroup): nonzeros per thread and per row block, and the default grid
-// (measured at n = 1M: 4 nonzeros per thread, or grids of 1024-4096, are
-// no faster; 512 is slower)
+// (measured at n = 1M: 4 nonzeros per thread is no faster; grids of 1024
+// to 4096 tie in FP64, 1024 is fastest in FP32 and leaves the fewest
+// partials to add; 512 is slower)
 constexpr int kPipeE = 8;
 constexpr int kPipeTile = kPipeE * kBlock;
-constexpr int kPipeGrid = 2048;
+constexpr int kPipeGrid = 1024;
 
 enum State : int32_t {
   ST_RUNNING = 0,
