@@ -52,11 +52,13 @@ enum {
   PDNQP_MAX_ITER = 2,
   PDNQP_TIME_LIMIT = 3,
   PDNQP_NUMERICAL_ERROR = 4,
+  /* 5 and 6 are kept for primal and dual infeasibility, which the paper
+   * mentions without formulas or thresholds; no solve returns them. */
   /* The scaled test passed at the smallest internal tolerances of the
    * calibration (settings.external_halvings) but the KKT test on the
    * caller's unscaled problem did not (Section 4, termination and tolerance
    * calibration: such a point counts as a failure). */
-  PDNQP_INACCURATE = 5
+  PDNQP_INACCURATE = 7
 };
 
 /* Outer scaling modes (Section 3.1, eq. (scaled-problem)). */

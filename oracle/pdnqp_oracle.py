@@ -55,9 +55,10 @@ SOLVED = 1
 MAX_ITER = 2
 TIME_LIMIT = 3
 NUMERICAL_ERROR = 4
+# (5 and 6 are kept for primal and dual infeasibility, not detected)
 # the scaled test passed at the smallest internal tolerances of the
 # calibration but the external test on the unscaled problem did not
-INACCURATE = 5
+INACCURATE = 7
 
 INNER_CONVERGED = 0
 INNER_ITER_LIMIT = 1

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpdnqp.so")
 
 OK = 0
 E_INVALID, E_NOMEM, E_DEVICE, E_STATE = -1, -2, -3, -4
-SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR, INACCURATE = 1, 2, 3, 4, 5
+SOLVED, MAX_ITER, TIME_LIMIT, NUMERICAL_ERROR, INACCURATE = 1, 2, 3, 4, 7
 STATUS_NAMES = {SOLVED: "solved", MAX_ITER: "max_iter", TIME_LIMIT: "time_limit",
                 NUMERICAL_ERROR: "numerical_error", INACCURATE: "inaccurate"}
 SCALE_RUIZ_A, SCALE_NONE, SCALE_RUIZ_QA = 0, 1, 2
