@@ -64,6 +64,12 @@ def test_fp32_small_solve(P, seed):
     assert info["r_p"] == pytest.approx(rp, rel=1e-6, abs=1e-12)
     assert info["r_d"] == pytest.approx(rd, rel=1e-6, abs=1e-12)
     assert np.all(x >= prob["xl"]) and np.all(x <= prob["xu"])
+    # per-result error against the FP64 oracle: both runs reach the same
+    # stationary point here (measured: |dx| 5.7e-5 and 4.6e-7, objectives
+    # within 2.1e-8 relative, for seeds 1 and 2)
+    assert res_o.status == O.SOLVED
+    assert np.abs(x - res_o.x).max() <= 1e-3 * max(1.0, np.abs(res_o.x).max())
+    assert abs(info["objective"] - res_o.objective) <= 1e-6 * max(1.0, abs(res_o.objective))
     print(f"seed {seed}: FP32 objective {info['objective']:.6f} vs FP64 oracle "
           f"{res_o.objective:.6f}; |x32 - x64|_inf {np.abs(x - res_o.x).max():.2e}; "
           f"unscaled r_p {rp:.2e} r_d {rd:.2e} (oracle {res_o.r_p:.2e}, {res_o.r_d:.2e})")
