@@ -175,6 +175,11 @@ typedef struct pdnqp_settings {
                               trial (the column-panel product and the A' product; a launch
                               tuning knob: it changes only the order in which per-workgroup
                               acceptance sums are added): 0 (default) 1024, else 2..4096 */
+  double kkt_pass_limit;   /* [paper] KKT pass limit: cumulative inner matrix passes, +inf
+                              (parameter table).  One pass = one inner trial (one product
+                              each with H_k, B and B'), counted over the whole solve and
+                              tested at the periodic checks of the inner iteration; reaching it
+                              ends the solve with PDNQP_MAX_ITER.  Must be >= 1 */
 } pdnqp_settings;
 
 /* Per-solve report. */

@@ -64,6 +64,7 @@ INNER_CONVERGED = 0
 INNER_ITER_LIMIT = 1
 INNER_NUMERICAL_ERROR = 2
 INNER_TIME_LIMIT = 3
+INNER_PASS_LIMIT = 4
 
 
 @dataclass
@@ -74,6 +75,11 @@ class Settings:
     max_outer: int = 2**31 - 1
     max_inner: int = 40000
     time_limit: float = math.inf
+    # KKT pass limit: cumulative inner matrix passes (the paper's table:
+    # +inf).  [reading] one pass = one trial (one product each with H_k, B
+    # and B'), counted over the whole solve and tested at the periodic
+    # checks, like the time limit; reaching it ends the solve with MAX_ITER
+    kkt_pass_limit: float = math.inf
     sigma_init: float = 20.0
     theta_sigma: float = 0.25
     delta_gamma: float = 1e-2
@@ -686,6 +692,8 @@ def inner_solve(state: InnerState, omega, delta_a, delta_r, st: Settings,
             cnt.restarts += 1
         else:
             state.kkt_prev = k_cand
+        if cnt.trials >= st.kkt_pass_limit:
+            return INNER_PASS_LIMIT, omega
         if at_limit:
             return INNER_ITER_LIMIT, omega
         if time.monotonic() > deadline:
@@ -879,6 +887,10 @@ def solve(prob, st: Settings = None, x0=None, lam0=None, trace: Trace = None):
             break
         if ist == INNER_TIME_LIMIT:
             status = TIME_LIMIT
+            x = x_in
+            break
+        if ist == INNER_PASS_LIMIT:
+            status = MAX_ITER
             x = x_in
             break
         if ist == INNER_ITER_LIMIT:

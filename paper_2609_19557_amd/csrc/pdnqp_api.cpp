@@ -132,6 +132,7 @@ void pdnqp_default_settings(pdnqp_settings *s) {
   s->fp32_stall = 50;
   s->external_halvings = 7;
   s->delta0 = 1.0;
+  s->kkt_pass_limit = std::numeric_limits<double>::infinity();
 }
 
 size_t pdnqp_settings_size(void) { return sizeof(pdnqp_settings); }
@@ -163,7 +164,8 @@ int pdnqp_create(pdnqp_solver **out, int32_t n, int32_t m, const int32_t *Qp, co
         !(st.fp32_promote >= 0) || !(st.delta_floor >= 0) || !std::isfinite(st.delta_floor) ||
         st.fp32_stall < 0 || st.external_halvings < 0 || st.external_halvings > 30 ||
         !(st.delta0 > 0) || !std::isfinite(st.delta0) || st.col_panels < 0 || st.col_panels > 2 ||
-        st.stream_grid < 0 || st.stream_grid == 1 || st.stream_grid > 4096)
+        st.stream_grid < 0 || st.stream_grid == 1 || st.stream_grid > 4096 ||
+        !(st.kkt_pass_limit >= 1.0))
       return fail(PDNQP_E_INVALID, "invalid settings value");
     std::string err;
     if (!check_csr(n, n, Qp, Qi, Qx, "Q", err)) return fail(PDNQP_E_INVALID, err);

@@ -1289,7 +1289,9 @@ struct BSolver {
         kind = 0;
         c.kkt_prev = kc;
       }
-      c.state = (c.t_call >= uni(I.st.max_inner)) ? ST_ITER_LIMIT : ST_RUNNING;
+      c.state = ((double)c.trials >= I.st.kkt_pass_limit)
+                    ? ST_PASS_LIMIT
+                    : ((c.t_call >= uni(I.st.max_inner)) ? ST_ITER_LIMIT : ST_RUNNING);
     }
     if (c.trace_checks_n < uni(I.st.trace_trials)) {
       if (threadIdx.x == 0) {
@@ -1709,6 +1711,10 @@ struct BSolver {
       }
       if (ist == ST_RUNNING) {
         status = PDNQP_TIME_LIMIT;
+        break;
+      }
+      if (ist == ST_PASS_LIMIT) {
+        status = PDNQP_MAX_ITER;
         break;
       }
       if (ist == ST_ITER_LIMIT) {

@@ -684,7 +684,9 @@ __global__ __launch_bounds__(kDecideThreads) void k_check_decide(Ctrl *__restric
       kind = 0;
       c->kkt_prev = kc;
     }
-    c->state = (c->t_call >= p.max_inner) ? ST_ITER_LIMIT : ST_RUNNING;
+    c->state = ((double)c->trials >= p.pass_limit)
+                   ? ST_PASS_LIMIT
+                   : ((c->t_call >= p.max_inner) ? ST_ITER_LIMIT : ST_RUNNING);
   }
   c->check_kind = kind;
   c->check_which = which;

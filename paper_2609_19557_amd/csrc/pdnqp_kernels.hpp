@@ -36,6 +36,7 @@ enum State : int32_t {
   ST_CONVERGED = 2,
   ST_NUMERR = 3,
   ST_ITER_LIMIT = 4,
+  ST_PASS_LIMIT = 5,  // the KKT pass limit was reached at a check
 };
 
 // Ticket counters of the "last workgroup finishes the reduction" pattern.
@@ -107,6 +108,7 @@ struct InnerParams {
   double h_norm;       // ||h||_inf = ||b_E||_inf
   double shrink_safety, shrink_min, shrink_max;
   double restart_suff, restart_nec, restart_art;
+  double pass_limit;   // KKT pass limit (cumulative trials of the solve)
 };
 
 template <typename T>

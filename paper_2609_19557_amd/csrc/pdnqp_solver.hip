@@ -370,6 +370,7 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   ip_ = InnerParams{};
   ip_.n = n; ip_.m = m; ip_.me = qp_.me; ip_.mi = mi; ip_.dw = n + mi + m;
   ip_.stream_grid = st_.stream_grid;
+  ip_.pass_limit = st_.kkt_pass_limit;
   timers_.resize(TM_COUNT);
   timers_[TM_XTRIAL].name = "xtrial";
   timers_[TM_QA].name = "qa_spmv";
@@ -940,6 +941,10 @@ int Solver::solve(double eps_abs, double eps_rel, const double *x0, const double
     }
     if (ist == ST_RUNNING) {  // deadline inside the inner solve
       status = PDNQP_TIME_LIMIT;
+      break;
+    }
+    if (ist == ST_PASS_LIMIT) {
+      status = PDNQP_MAX_ITER;
       break;
     }
     // with the learned controller, the inner iteration budget ends the inner

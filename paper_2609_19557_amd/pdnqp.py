@@ -80,6 +80,7 @@ class Settings(ctypes.Structure):
         ("delta0", ctypes.c_double),
         ("col_panels", ctypes.c_int32),
         ("stream_grid", ctypes.c_int32),
+        ("kkt_pass_limit", ctypes.c_double),
     ]
 
 

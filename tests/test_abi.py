@@ -156,7 +156,8 @@ def test_null_handle_calls_are_errors(P):
                                          ("external_halvings", 31), ("delta0", 0.0),
                                          ("delta0", float("nan")), ("col_panels", 3),
                                          ("stream_grid", -1), ("stream_grid", 1),
-                                         ("stream_grid", 4097)])
+                                         ("stream_grid", 4097), ("kkt_pass_limit", 0.5),
+                                         ("kkt_pass_limit", float("nan"))])
 def test_rejects_bad_extension_settings(P, field, value):
     p = qpgen.workload("small", 3)
     _expect_invalid(P, *_args(p), match="settings", **{field: value})
@@ -171,6 +172,8 @@ def test_extension_defaults(P):
     assert s.fp32_stall == 50
     assert s.external_halvings == 7
     assert s.delta0 == 1.0
+    assert (s.col_panels, s.stream_grid) == (0, 0)
+    assert s.kkt_pass_limit == float("inf")  # the paper's table
 
 
 def test_batch_and_network_argument_errors(P):

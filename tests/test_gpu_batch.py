@@ -166,6 +166,13 @@ def test_batch_limits(P):
     st2 = O.Settings(time_limit=0.0)
     _, out2, _ = _solve_batch(P, probs, st2)
     assert all(o[2]["status"] == O.TIME_LIMIT for o in out2)
+    # the KKT pass limit ends each instance at the oracle's check
+    st3 = O.Settings(outer_scaling=2, kkt_pass_limit=250)
+    _, out3, _ = _solve_batch(P, probs, st3)
+    for p, (x, lam, info) in zip(probs, out3):
+        res_o = O.solve(p, st3)
+        assert info["status"] == res_o.status == O.MAX_ITER
+        assert info["inner_trials"] == res_o.counters.trials
 
 
 def test_batch_fp32_tracks_oracle_and_solves(P):

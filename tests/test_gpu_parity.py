@@ -41,7 +41,7 @@ def _gpu_kwargs(st: O.Settings):
             "restart_art", "shrink_safety", "shrink_min", "shrink_max", "omega0", "sigma_growth",
             "sigma_max", "sigma0_min", "sigma0_max", "lanczos_iters", "gamma_override",
             "step_boost", "outer_scaling", "anderson_mem", "anderson_reg", "delta_floor",
-            "external_halvings", "delta0"]
+            "external_halvings", "delta0", "kkt_pass_limit"]
     kw = {k: getattr(st, k) for k in keys}
     kw["max_outer"] = int(min(st.max_outer, 2**62))
     kw["penalty_gate"] = int(st.penalty_gate)
@@ -294,6 +294,22 @@ def test_time_limit_and_outer_limit(P):
     s2 = P.Solver.from_problem(prob, max_outer=1)
     _, _, info2 = s2.solve(1e-4, 1e-4)
     assert info2["status"] == O.MAX_ITER and info2["outer_iters"] == 1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_kkt_pass_limit_matches_oracle(P, precision):
+    """The KKT pass limit ends the solve with MAX_ITER at the same periodic
+    check as the oracle (same trial count; in FP64 the same iterates)."""
+    prob = qpgen.workload("small", 1)
+    st = _oracle_settings(outer_scaling=2, kkt_pass_limit=300)
+    res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, iters=400, trials=800,
+                                               precision=precision)
+    assert res_o.status == info["status"] == O.MAX_ITER
+    if precision == 0:
+        assert info["inner_trials"] == res_o.counters.trials
+        assert_iterate_parity(tr, t)
+        np.testing.assert_allclose(x, res_o.x, atol=1e-8 * max(1, np.abs(res_o.x).max()))
+    assert 300 <= info["inner_trials"] < 300 + 2 * 64
 
 
 def test_warm_start_arguments(P):

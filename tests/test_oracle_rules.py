@@ -463,3 +463,21 @@ def test_calibration_limit_reports_inaccurate(monkeypatch):
     res = O.solve(qpgen.tiny_qp(3, 1, 1, 2), O.Settings(max_outer=20000))
     assert res.status == O.INACCURATE
     assert res.halvings == 7 and len(calls) == 8 + 1   # 8 candidates, then the final report
+
+
+def test_kkt_pass_limit_ends_the_solve_at_a_check():
+    """The KKT pass limit (parameter table, +inf by default): the solve ends
+    with MAX_ITER at the first periodic check at which the cumulative trial
+    count has reached the limit, and the same run without the limit passes
+    that point."""
+    prob = qpgen.workload("small", 1)
+    tr = O.Trace(max_iters=0)
+    res = O.solve(prob, O.Settings(outer_scaling=2, kkt_pass_limit=300), trace=tr)
+    assert res.status == O.MAX_ITER
+    # checks record (kind, accepted since formation, candidate, trials so far, ratio)
+    hit = [c for c in tr.checks if c[0] != "converged" and c[3] >= 300]
+    assert hit and tr.checks[-1] is hit[0]
+    trials = res.counters.trials
+    assert trials == hit[0][3] and 300 <= trials < 300 + 2 * 64
+    free = O.solve(prob, O.Settings(outer_scaling=2, max_outer=60))
+    assert free.counters.trials > trials
