@@ -312,6 +312,28 @@ def test_kkt_pass_limit_matches_oracle(P, precision):
     assert 300 <= info["inner_trials"] < 300 + 2 * 64
 
 
+def test_torch_allocator_and_stream_give_identical_results(P):
+    """With torch's caching allocator and current stream plumbed in
+    (settings dev_alloc/dev_free/hip_stream), a solve returns bit-identical
+    results to the library's own allocations and stream, and its device
+    memory comes from torch."""
+    import torch
+    prob = qpgen.workload("small", 2)
+    kw = dict(outer_scaling=2, max_outer=20, trace_iters=200)
+    s0 = P.Solver.from_problem(prob, **kw)
+    x0, l0, i0 = s0.solve(1e-4, 1e-4)
+    torch.cuda.reset_peak_memory_stats()
+    before = torch.cuda.memory_allocated()
+    s1 = P.Solver.from_problem(prob, use_torch=True, **kw)
+    assert torch.cuda.memory_allocated() > before
+    x1, l1, i1 = s1.solve(1e-4, 1e-4)
+    assert np.array_equal(x0, x1) and np.array_equal(l0, l1)
+    assert i0["inner_accepted"] == i1["inner_accepted"] and i0["status"] == i1["status"]
+    assert np.array_equal(s0.trace()["w"], s1.trace()["w"])
+    s1.close()
+    assert torch.cuda.memory_allocated() == before
+
+
 def test_warm_start_arguments(P):
     prob = qpgen.workload("small", 7)
     rng = np.random.default_rng(0)
