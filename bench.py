@@ -212,6 +212,11 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=256)
     ap.add_argument("--tol-time-limit", type=float, default=90.0)
+    ap.add_argument("--tol", type=float, default=1e-4,
+                    help="eps_abs = eps_rel of the time-to-tolerance solve")
+    ap.add_argument("--tol-verbose", action="store_true",
+                    help="the time-to-tolerance solve prints one line per outer step to stderr "
+                         "(the library's settings.verbose)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="fp64 (the paper's arithmetic, default); fp32: FP32 matrix values and "
                          "inner vectors with FP64 reductions, FP64 outer update and final check "
@@ -309,18 +314,20 @@ def main():
     if not args.no_time_to_tol:
         st = P.Solver.from_problem(prob, use_torch=True, outer_scaling=P.SCALE_RUIZ_QA,
                                    time_limit_s=args.tol_time_limit, precision=prec,
-                                   col_panels=args.col_panels, stream_grid=args.stream_grid)
+                                   col_panels=args.col_panels, stream_grid=args.stream_grid,
+                                   verbose=1 if args.tol_verbose else 0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, _, inf2 = st.solve(1e-4, 1e-4)
+        _, _, inf2 = st.solve(args.tol, args.tol)
         torch.cuda.synchronize()
-        ttt = {"seconds": round(time.perf_counter() - t1, 3), "status": inf2["status_name"],
+        ttt = {"tol": args.tol, "seconds": round(time.perf_counter() - t1, 3),
+               "status": inf2["status_name"],
                "outer_iters": inf2["outer_iters"], "inner_accepted": inf2["inner_accepted"],
                "outer_scaling": "ruiz_qa", "r_p": inf2["r_p"], "r_d": inf2["r_d"],
                "s_p": inf2["s_p"], "s_d": inf2["s_d"],
                "inner_iters_per_s": round(inf2["inner_accepted"] / max(1e-9, inf2["solve_s"]), 1)}
         st.close()
-        print(f"[bench] time-to-1e-4: {ttt}", file=sys.stderr, flush=True)
+        print(f"[bench] time-to-{args.tol:g}: {ttt}", file=sys.stderr, flush=True)
 
     other = None
     if not args.no_other_precision:
