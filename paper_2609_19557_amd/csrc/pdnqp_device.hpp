@@ -155,61 +155,6 @@ __device__ __forceinline__ void for_elems(int n, int b, int nb, F &&f) {
   for (int i = b * kBlock + threadIdx.x; i < n; i += nb * kBlock) f(i);
 }
 
-// CSR-stream row sums of rows [r0, r1) of M x.  The workgroup loads the
-// block's nonzeros with unit stride (kStreamE per thread, all independent),
-// gathers x for all of them at once, stages the products in LDS and lets
-// one thread per row add its products in order; f(row, sum) runs on that
-// thread.  A block holding a single row longer than a tile sums it with a
-// block reduction instead and calls f on thread 0.
-template <typename T, typename F>
-__device__ __forceinline__ void stream_rows(const CsrT<T> &M, const T *__restrict__ x, int r0,
-                                            int r1, T *__restrict__ sprod, F &&f) {
-  const int base = M.p[r0];
-  const int cnt = M.p[r1] - base;
-  if (cnt <= kTile) {
-    int col[kStreamE];
-    T val[kStreamE];
-#pragma unroll
-    for (int e = 0; e < kStreamE; ++e) {
-      const int k = e * kBlock + threadIdx.x;
-      col[e] = 0;
-      val[e] = T(0);
-      if (k < cnt) {
-        col[e] = __builtin_nontemporal_load(&M.i[base + k]);
-        val[e] = __builtin_nontemporal_load(&M.v[base + k]);
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < kStreamE; ++e) {
-      const int k = e * kBlock + threadIdx.x;
-      if (k < cnt) sprod[k] = val[e] * x[col[e]];
-    }
-    __syncthreads();
-    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
-      const int a = M.p[row] - base;
-      const int b = M.p[row + 1] - base;
-      T s = T(0);
-      for (int k = a; k < b; ++k) s += sprod[k];
-      f(row, s);
-    }
-    __syncthreads();
-  } else {
-    __shared__ T red[kWaves];
-    T s = T(0);
-    for (int k = threadIdx.x; k < cnt; k += kBlock) s += M.v[base + k] * x[M.i[base + k]];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      T t = red[0];
-      for (int w = 1; w < kWaves; ++w) t += red[w];
-      f(r0, t);
-    }
-    __syncthreads();
-  }
-}
-
 // One row block of a CSR-stream product as a pipeline stage: the matrix it
 // belongs to (tag tells the caller which), its rows [r0, r1), its nonzeros
 // [base, base + cnt) and, once loaded, this thread's E of them.
@@ -264,8 +209,10 @@ __device__ __forceinline__ void tile_load(StreamTile<T, E> &t) {
 // the end of each step, so a workgroup keeps the matrix stream and the
 // gathers of x busy at the same time instead of in turn.  Products are
 // staged in LDS (sprod: E * kBlock entries) and one thread per row adds its
-// products in order, as in stream_rows, so the sums are the same;
-// emit(tag, row, sum) runs on that thread.
+// products in order, so each row's sum does not depend on the grid;
+// emit(tag, row, sum) runs on that thread.  A block holding a single row
+// longer than a tile sums it with a block reduction instead and calls emit
+// on thread 0.
 template <typename T, int E, typename Sel, typename Emit>
 __device__ __forceinline__ void stream_pipelined(int it0, int items, int step,
                                                  const T *__restrict__ x, T *__restrict__ sprod,

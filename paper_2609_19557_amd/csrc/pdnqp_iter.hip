@@ -3,8 +3,8 @@
 // double for the FP64 path, float for the FP32-bulk path.  Every reduction
 // (acceptance sums, KKT and restart norms) accumulates in FP64 whatever T is.
 //
-// Per trial: k_xtrial -> k_qa_stream -> k_at_stream -> k_decide.  Per
-// check: k_flush -> k_check_spmv -> k_check -> k_check_decide -> k_apply ->
+// Per trial: k_xtrial -> k_qa_stream (or, with two column panels,
+// k_qa_panels -> k_qa_rows) -> k_at_stream -> k_decide.  Per check: k_flush -> k_check_spmv -> k_check -> k_check_decide -> k_apply ->
 // k_apply_done.  Every kernel reads the device control block and does
 // nothing when its phase is not due, so the host can enqueue fixed chunks.
 #include "pdnqp_device.hpp"
