@@ -4,7 +4,8 @@
 // (acceptance sums, KKT and restart norms) accumulates in FP64 whatever T is.
 //
 // Per trial: k_xtrial -> k_qa_stream (or, with two column panels,
-// k_qa_panels -> k_qa_rows) -> k_at_stream -> k_decide.  Per check: k_flush -> k_check_spmv -> k_check -> k_check_decide -> k_apply ->
+// k_qa_panels -> k_qa_rows) -> k_at_stream -> k_decide.  Per check:
+// k_flush -> k_check_spmv -> k_check -> k_check_decide -> k_apply ->
 // k_apply_done.  Every kernel reads the device control block and does
 // nothing when its phase is not due, so the host can enqueue fixed chunks.
 #include "pdnqp_device.hpp"
@@ -239,44 +240,54 @@ __global__ __launch_bounds__(kBlock) void k_qa_panels(Ctrl *__restrict__ c, Iter
       [&](int tag, int row, T s) { (tag ? pa : pq)[row] = s; });
 }
 
+// The constraint rows of the two-panel form: panel sums of A x_tr (panel 0
+// first) and the row-local trial; one acceptance partial per workgroup.
+// (The Q rows' panel sums are formed where they are first needed, in the
+// epilogue of the A' product.)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_qa_rows(Ctrl *__restrict__ c, InnerParams p,
-                                                    IterVecs<T> v, QAPanels<T> P, int gq, int ga) {
+                                                    IterVecs<T> v, QAPanels<T> P, int ga) {
   if (c->state != ST_RUNNING) return;
-  const int nxt = c->cur ^ 1;
-  if ((int)blockIdx.x < gq) {
-    const T *__restrict__ xt = v.X[nxt];
-    T *__restrict__ qxt = v.QX[nxt];
-    const T *__restrict__ qd = v.qdiag;
-    for_elems(p.n, blockIdx.x, gq,
-              [&](int i) { qxt[i] = (P.pq0[i] + P.pq1[i]) + qd[i] * xt[i]; });
-  } else {
-    const int b = blockIdx.x - gq;
-    RowTrial<T> rt(c, p);
-    for_elems(p.m, b, ga, [&](int j) { rt(v, j, P.pa0[j] + P.pa1[j]); });
-    rt.reduce(v, b);
-  }
+  const int b = (int)blockIdx.x;
+  if (b >= ga) return;  // no constraint rows: one idle workgroup
+  RowTrial<T> rt(c, p);
+  for_elems(p.m, b, ga, [&](int j) { rt(v, j, P.pa0[j] + P.pa1[j]); });
+  rt.reduce(v, b);
 }
 
 // Trial step, sparse part 2, CSR-stream form: row blocks of A' (A' y_tr)
-// and the x-block acceptance sums |dx (H dx)|, |dx (A' dy)| (FP64).
+// and the x-block acceptance sums |dx (H dx)|, |dx (A' dy)| (FP64).  With
+// the two-panel form (pq0, pq1 non-null) the epilogue also forms Q x_tr of
+// its x element from the two panels' partial sums (panel 0 first) and the
+// diagonal, the Q-row part of the first product that k_qa_rows leaves out.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_at_stream(Ctrl *__restrict__ c, InnerParams p,
-                                                      IterVecs<T> v, CsrT<T> AT) {
+                                                      IterVecs<T> v, CsrT<T> AT,
+                                                      const T *__restrict__ pq0,
+                                                      const T *__restrict__ pq1) {
   if (c->state != ST_RUNNING) return;
   __shared__ T sprod[kPipeTile];
   const int cur = c->cur;
   const int nxt = cur ^ 1;
   const double gi = p.gamma_inv;
   const T *__restrict__ yt = v.Y[nxt];
+  const bool form_qx = pq0 != nullptr;
   double s5 = 0.0, s6 = 0.0;
   stream_pipelined<T, kPipeE>(
       (int)blockIdx.x, AT.nrb, (int)gridDim.x, yt, sprod,
       [&](int b, StreamTile<T, kPipeE> &t) { tile_bounds(AT, b, 0, t); },
       [&](int, int i, T a) {
         v.ATY[nxt][i] = a;
-        const double dx = (double)v.X[nxt][i] - (double)v.X[cur][i];
-        const double hdx = ((double)v.QX[nxt][i] - (double)v.QX[cur][i]) + gi * dx;
+        const T xn = v.X[nxt][i];
+        T qn;
+        if (form_qx) {
+          qn = (pq0[i] + pq1[i]) + v.qdiag[i] * xn;
+          v.QX[nxt][i] = qn;
+        } else {
+          qn = v.QX[nxt][i];
+        }
+        const double dx = (double)xn - (double)v.X[cur][i];
+        const double hdx = ((double)qn - (double)v.QX[cur][i]) + gi * dx;
         const double ady = (double)a - (double)v.ATY[cur][i];
         s5 += fabs(dx * hdx);
         s6 += fabs(dx * ady);
@@ -910,16 +921,15 @@ template <typename T>
 void launch_qa_rows(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                     const QAPanelSet<T> &P, LaunchEvents ev) {
   QAPanels<T> k{P.q[0], P.q[1], P.a[0], P.a[1], P.pq[0], P.pq[1], P.pa[0], P.pa[1]};
-  const int gq = qa_rows_blocks(p.n);
   const int ga = p.m ? qa_rows_blocks(p.m) : 0;
-  launch_ev(k_qa_rows<T>, dim3(gq + ga), dim3(kBlock), st, ev, c, p, v, k, gq, ga);
+  launch_ev(k_qa_rows<T>, dim3(nz(ga)), dim3(kBlock), st, ev, c, p, v, k, ga);
 }
 
 template <typename T>
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
-               const CsrT<T> &AT, LaunchEvents ev) {
+               const CsrT<T> &AT, LaunchEvents ev, const T *pq0, const T *pq1) {
   launch_ev(k_at_stream<T>, dim3(at_grid(AT.nrb, p.stream_grid)), dim3(kBlock), st, ev, c, p, v,
-            AT);
+            AT, pq0, pq1);
 }
 
 void launch_decide(hipStream_t st, Ctrl *c, const InnerParams &p, const double *partial,
@@ -1003,7 +1013,7 @@ void launch_cast(hipStream_t st, D *dst, const S *src, int64_t n) {
   template void launch_qa<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,      \
                              const CsrT<T> &, const CsrT<T> &, LaunchEvents);                    \
   template void launch_at<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &,      \
-                             const CsrT<T> &, LaunchEvents);                                     \
+                             const CsrT<T> &, LaunchEvents, const T *, const T *);               \
   template void launch_qa_panels<T>(hipStream_t, Ctrl *, const InnerParams &,                    \
                                     const IterVecs<T> &, const QAPanelSet<T> &, LaunchEvents);   \
   template void launch_qa_rows<T>(hipStream_t, Ctrl *, const InnerParams &, const IterVecs<T> &, \

@@ -198,9 +198,12 @@ void launch_xtrial(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs
 template <typename T>
 void launch_qa(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
                const CsrT<T> &Qoff, const CsrT<T> &A, LaunchEvents ev = {});
+// A' product and x-block sums; pq0/pq1 (the two-panel form's Q partial
+// sums, or null) make its epilogue form Q x_tr as well
 template <typename T>
 void launch_at(hipStream_t st, Ctrl *c, const InnerParams &p, const IterVecs<T> &v,
-               const CsrT<T> &AT, LaunchEvents ev = {});
+               const CsrT<T> &AT, LaunchEvents ev = {}, const T *pq0 = nullptr,
+               const T *pq1 = nullptr);
 // Two-panel form of launch_qa: Q_off and A split by columns at n/2, each
 // half a CSR over all rows with its own stream row blocks, and the per-row
 // partial sums of each half (device buffers of n and m values).

@@ -390,11 +390,14 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
   if (fp32_ ? panels32_ : panels64_) {
     // the two-panel form: values and indices once, both panels' row
     // pointers, x_tr once, one partial per row and panel written; then the
-    // partials read back, and the Q and A row epilogues of the one-launch form
+    // A partials read back with the A row epilogue of the one-launch form;
+    // the Q partials and the diagonal are read, and Q x_tr written, by the
+    // A' launch instead of reading Q x_tr
     timers_[TM_QA].name = "qa_panels";
     timers_[TM_QA].bytes = (4.0 + vb) * (nzo + nza) + 8.0 * (n + 1) + 8.0 * (m + 1) + vb * n +
                            2.0 * vb * (n + m);
-    timers_[TM_QA_ROWS].bytes = 2.0 * vb * (n + m) + 3.0 * vb * n + 15.0 * vb * me + 20.0 * vb * mi;
+    timers_[TM_QA_ROWS].bytes = 2.0 * vb * m + 15.0 * vb * me + 20.0 * vb * mi;
+    timers_[TM_AT].bytes += 3.0 * vb * n;
   }
   return PDNQP_OK;
 }
@@ -698,7 +701,14 @@ void Solver::enqueue_chunk(int slots, bool sampled, const IterVecs<T> &iv, const
     } else {
       timed_launch(TM_QA, [&](LaunchEvents e) { launch_qa<T>(stream_, ctrl_, ip_, iv, Qo, A, e); });
     }
-    timed_launch(TM_AT, [&](LaunchEvents e) { launch_at<T>(stream_, ctrl_, ip_, iv, AT, e); });
+    timed_launch(TM_AT, [&](LaunchEvents e) {
+      if (panels) {
+        const QAPanelSet<T> &ps = panel_set<T>();
+        launch_at<T>(stream_, ctrl_, ip_, iv, AT, e, ps.pq[0], ps.pq[1]);
+      } else {
+        launch_at<T>(stream_, ctrl_, ip_, iv, AT, e);
+      }
+    });
     timed_launch(TM_DECIDE, [&](LaunchEvents e) {
       launch_decide(stream_, ctrl_, ip_, iv.partial, iv.trace_tr, Qo.nrb, A.nrb, AT.nrb, e,
                     panels);
