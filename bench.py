@@ -214,6 +214,9 @@ def main():
     ap.add_argument("--tol-time-limit", type=float, default=90.0)
     ap.add_argument("--tol", type=float, default=1e-4,
                     help="eps_abs = eps_rel of the time-to-tolerance solve")
+    ap.add_argument("--tol-settings", default="{}",
+                    help="JSON object of further pdnqp_settings fields for the time-to-tolerance "
+                         "solve, e.g. '{\"anderson_mem\": 5}'")
     ap.add_argument("--tol-verbose", action="store_true",
                     help="the time-to-tolerance solve prints one line per outer step to stderr "
                          "(the library's settings.verbose)")
@@ -315,12 +318,14 @@ def main():
         st = P.Solver.from_problem(prob, use_torch=True, outer_scaling=P.SCALE_RUIZ_QA,
                                    time_limit_s=args.tol_time_limit, precision=prec,
                                    col_panels=args.col_panels, stream_grid=args.stream_grid,
-                                   verbose=1 if args.tol_verbose else 0)
+                                   verbose=1 if args.tol_verbose else 0,
+                                   **json.loads(args.tol_settings))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, _, inf2 = st.solve(args.tol, args.tol)
         torch.cuda.synchronize()
-        ttt = {"tol": args.tol, "seconds": round(time.perf_counter() - t1, 3),
+        ttt = {"tol": args.tol, "settings": json.loads(args.tol_settings),
+               "seconds": round(time.perf_counter() - t1, 3),
                "status": inf2["status_name"],
                "outer_iters": inf2["outer_iters"], "inner_accepted": inf2["inner_accepted"],
                "outer_scaling": "ruiz_qa", "r_p": inf2["r_p"], "r_d": inf2["r_d"],
