@@ -271,8 +271,8 @@ int Solver::init(HostQP &&qp, const pdnqp_settings &st, std::string &err) {
 
   const int GQ = pick_G(nzq, n), GA = pick_G(nza, m), GT = pick_G(nza, n);
   // CSR-stream row blocks of the three matrices
-  // (tile: nonzeros per block, kTile for the single-stage kernels, kPipeTile
-  // for the pipelined ones: A' and the column panels)
+  // (tile: nonzeros per block; kPipeTile for the matrices the pipelined
+  // trial products stream: Q_off, A, A' and the column panels)
   auto blocks_of = [&](const std::vector<int32_t> &rp, int32_t rows, int32_t *&dev,
                        int32_t &nrb, int32_t tile) -> bool {
     // row boundaries of the nrb blocks, then the nonzero offset of each
