@@ -172,9 +172,10 @@ typedef struct pdnqp_settings {
                               sums): 0 (default) when the gathered vector exceeds one XCD's L2
                               (4 MiB), 1 never, 2 always */
   int32_t stream_grid;     /* workgroups of the pipelined CSR-stream product launches of a
-                              trial (the column-panel product and the A' product; a launch
-                              tuning knob: it changes only the order in which per-workgroup
-                              acceptance sums are added): 0 (default) 1024, else 2..4096 */
+                              trial (the first product, in its one-launch or column-panel
+                              form, and the A' product; a launch tuning knob: it changes only
+                              the order in which per-workgroup acceptance sums are added):
+                              0 (default) 1024, else 2..4096 */
   double kkt_pass_limit;   /* [paper] KKT pass limit: cumulative inner matrix passes, +inf
                               (parameter table).  One pass = one inner trial (one product
                               each with H_k, B and B'), counted over the whole solve and
