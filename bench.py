@@ -315,11 +315,11 @@ def main():
 
     ttt = None
     if not args.no_time_to_tol:
-        st = P.Solver.from_problem(prob, use_torch=True, outer_scaling=P.SCALE_RUIZ_QA,
-                                   time_limit_s=args.tol_time_limit, precision=prec,
-                                   col_panels=args.col_panels, stream_grid=args.stream_grid,
-                                   verbose=1 if args.tol_verbose else 0,
-                                   **json.loads(args.tol_settings))
+        tkw = dict(outer_scaling=P.SCALE_RUIZ_QA, time_limit_s=args.tol_time_limit,
+                   precision=prec, col_panels=args.col_panels, stream_grid=args.stream_grid,
+                   verbose=1 if args.tol_verbose else 0)
+        tkw.update(json.loads(args.tol_settings))
+        st = P.Solver.from_problem(prob, use_torch=True, **tkw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, _, inf2 = st.solve(args.tol, args.tol)
@@ -328,7 +328,9 @@ def main():
                "seconds": round(time.perf_counter() - t1, 3),
                "status": inf2["status_name"],
                "outer_iters": inf2["outer_iters"], "inner_accepted": inf2["inner_accepted"],
-               "outer_scaling": "ruiz_qa", "r_p": inf2["r_p"], "r_d": inf2["r_d"],
+               "outer_scaling": {P.SCALE_RUIZ_A: "ruiz_a", P.SCALE_NONE: "none",
+                                 P.SCALE_RUIZ_QA: "ruiz_qa"}[tkw["outer_scaling"]],
+               "r_p": inf2["r_p"], "r_d": inf2["r_d"],
                "s_p": inf2["s_p"], "s_d": inf2["s_d"],
                "inner_iters_per_s": round(inf2["inner_accepted"] / max(1e-9, inf2["solve_s"]), 1)}
         st.close()
