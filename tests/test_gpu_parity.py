@@ -347,18 +347,35 @@ def test_warm_start_arguments(P):
     assert_iterate_parity(tr, s.trace())
 
 
-@pytest.mark.timeout(600)
-def test_medium_first_1000_iterations(P):
-    """n = 100,000 (m = 50,000): every entry of w and y after each of the
-    first 1000 accepted iterations, spanning several outer steps, stopping
-    checks and restarts, at 1e-9 relative, with identical decisions."""
+@pytest.fixture(scope="module")
+def medium_oracle():
     prob = qpgen.workload("medium", 1)
     st = _oracle_settings(max_outer=7, max_inner=256, outer_scaling=2)
-    res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, iters=1000, trials=3000)
+    tr = O.Trace(max_iters=1000)
+    res_o = O.solve(prob, st, trace=tr)
+    return prob, st, tr, res_o
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("panels", [1, 2])
+def test_medium_first_1000_iterations(P, medium_oracle, panels):
+    """n = 100,000 (m = 50,000): every entry of w and y after each of the
+    first 1000 accepted iterations, spanning several outer steps, stopping
+    checks and restarts, at 1e-9 relative, with identical decisions; in the
+    one-launch form of the first product and in the two-panel form (forced
+    here: at this size x fits one XCD's L2), whose Q-row sums are formed in
+    the A' epilogue."""
+    prob, st, tr, res_o = medium_oracle
+    s = P.Solver.from_problem(prob, trace_iters=1000, trace_trials=3000, col_panels=panels,
+                              **_gpu_kwargs(st))
+    s.solve(st.eps_abs, st.eps_rel)
+    t = s.trace()
     assert_iterate_parity(tr, t, n_expect=1000)
     compared = assert_decision_parity(tr, t, window_of(tr))
     assert compared >= 12
     assert any(c[0] == "restart" for c in tr.checks[:compared])
+    if panels == 2:
+        assert "qa_panels" in {k["name"] for k in s.kernel_stats()}
 
 
 @pytest.mark.parametrize("precision", [0, 1])
