@@ -88,12 +88,14 @@ def test_fp32_edge_cases(P, name):
     assert np.abs(x - res_o.x).max() <= 1e-2 * max(1.0, np.abs(res_o.x).max())
 
 
-def test_fp32_medium_first_iterations(P):
+@pytest.mark.parametrize("panels", [1, 2])
+def test_fp32_medium_first_iterations(P, panels):
     prob = qpgen.workload("medium", 1)
     st = O.Settings(max_outer=1, max_inner=64, outer_scaling=0)
     tr = O.Trace(max_iters=20)
     O.solve(prob, st, trace=tr)
-    s = P.Solver.from_problem(prob, precision=P.FP32, trace_iters=20, **_gpu_kwargs(st))
+    s = P.Solver.from_problem(prob, precision=P.FP32, trace_iters=20, col_panels=panels,
+                              **_gpu_kwargs(st))
     s.solve(st.eps_abs, st.eps_rel)
     t = s.trace()
     for k in range(20):
