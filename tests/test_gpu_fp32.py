@@ -135,3 +135,30 @@ def test_fp32_promotes_below_its_attainable_tolerance(P):
         assert np.array_equal(xa, xb)
     print(f"promoted at outer step {k} of {info['outer_iters']}; "
           f"unscaled r_p {rp:.2e} r_d {rd:.2e}")
+
+
+@pytest.mark.parametrize("workload,seed,window,tol", [("small", 1, 1000, 1e-3),
+                                                      ("small", 2, 1000, 1e-3),
+                                                      ("medium", 1, 200, 1e-5),
+                                                      ("medium", 1, 500, 2e-3)])
+def test_fp32_tracking_over_long_windows(P, workload, seed, window, tol):
+    """FP32 bulk against the FP64 oracle over long windows of accepted
+    iterations (Q-aware scaling, spanning checks and restarts).  FP32
+    rounding is amplified along the trajectory; measured worst relative
+    deviations: small seeds 1 and 2 5.1e-5 and 3.4e-5 over 1000 iterations;
+    n = 100k 9.4e-7 over 200 and 1.7e-4 over 500.  The accept/reject
+    sequences first differ after these windows (trials 1290-1844)."""
+    prob = qpgen.workload(workload, seed)
+    st = O.Settings(max_outer=40 if workload == "small" else 7,
+                    max_inner=40000 if workload == "small" else 256, outer_scaling=2)
+    tr = O.Trace(max_iters=window)
+    O.solve(prob, st, trace=tr)
+    s = P.Solver.from_problem(prob, precision=P.FP32, trace_iters=window,
+                              trace_trials=4 * window, **_gpu_kwargs(st))
+    s.solve(st.eps_abs, st.eps_rel)
+    t = s.trace()
+    n = min(len(tr.w), t["w"].shape[0])
+    assert n == window
+    worst = max(max(_relmax(t["w"][k], tr.w[k]), _relmax(t["y"][k], tr.y[k])) for k in range(n))
+    print(f"{workload} seed {seed}: worst FP32 deviation over {n} iterations {worst:.2e}")
+    assert worst <= tol
