@@ -21,7 +21,7 @@ from tests.test_gpu_parity import (EDGE, _gpu_kwargs, assert_decision_parity,
 
 pytestmark = pytest.mark.gpu
 
-ITERS = 300
+ITERS = 1000
 
 
 @pytest.fixture(scope="module")
@@ -40,7 +40,7 @@ def _batch(seed, count, lo, hi):
 @pytest.fixture(scope="module")
 def parity_case():
     probs = _batch(7, 5, 200, 1200)
-    st = O.Settings(max_outer=8, outer_scaling=2)
+    st = O.Settings(max_outer=30, outer_scaling=2)  # at least 1000 accepted iterations each
     traces = []
     for p in probs:
         tr = O.Trace(max_iters=ITERS)
