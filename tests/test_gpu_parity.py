@@ -253,13 +253,18 @@ def _edge_cases():
 EDGE = _edge_cases()
 
 
+@pytest.mark.parametrize("grid", [0, 2])
 @pytest.mark.parametrize("panels", [1, 2])
 @pytest.mark.parametrize("name", sorted(EDGE))
-def test_edge_cases_iterate_parity(P, name, panels):
+def test_edge_cases_iterate_parity(P, name, panels, grid):
+    """Edge cases in both forms of the first product; with a grid of 2
+    workgroups per pipelined launch each workgroup walks all of its row
+    blocks in turn (empty blocks, a row longer than a tile between short
+    rows, a ragged last block)."""
     prob = EDGE[name]
     st = _oracle_settings(max_outer=12, outer_scaling=2)
     res_o, tr, (x, lam, info), t, s = run_pair(P, prob, st, iters=400, trials=800,
-                                               col_panels=panels)
+                                               col_panels=panels, stream_grid=grid)
     assert_iterate_parity(tr, t)
     assert_decision_parity(tr, t, window_of(tr))
     assert info["status"] == res_o.status
