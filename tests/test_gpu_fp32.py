@@ -75,12 +75,13 @@ def test_fp32_small_solve(P, seed):
           f"unscaled r_p {rp:.2e} r_d {rd:.2e} (oracle {res_o.r_p:.2e}, {res_o.r_d:.2e})")
 
 
+@pytest.mark.parametrize("panels", [1, 2])
 @pytest.mark.parametrize("name", sorted(EDGE))
-def test_fp32_edge_cases(P, name):
+def test_fp32_edge_cases(P, name, panels):
     prob = EDGE[name]
     st = O.Settings(max_outer=12, outer_scaling=2)
     res_o = O.solve(prob, st)
-    s = P.Solver.from_problem(prob, precision=P.FP32, **_gpu_kwargs(st))
+    s = P.Solver.from_problem(prob, precision=P.FP32, col_panels=panels, **_gpu_kwargs(st))
     x, lam, info = s.solve(st.eps_abs, st.eps_rel)
     assert np.all(np.isfinite(x)) and np.all(np.isfinite(lam))
     assert info["status"] in (O.SOLVED, O.MAX_ITER)
